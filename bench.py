@@ -1,0 +1,198 @@
+"""Benchmark of the PIC-MCC hot path on one MI355X.
+
+Prints ONE JSON line.  The headline `value` is particle-steps/s of the FP32 cell + offset
+path on the large single discharge (4096 cells, 1e7 electrons + 1e7 ions, 5 Pa Ar-like
+gas, 300 V at 13.56 MHz, sort every step), inputs resident in HBM, K steps replayed from
+a captured HIP graph and timed with HIP events on the library's stream.  The FP64 path on
+the same discharge and the batched 256-discharge scan are reported under "paths"; the
+roofline of the dominant kernel (k_main) and the oracle's CPU speed on a bounded sample
+of the same workload come alongside.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-paths] [--skip-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s: FP32-offset vs FP64 vs batched, at ≤1e-3 density err"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per particle-step of the fused pass: the whole record read once and
+# written once (FP32 cell + offset: 24 B record; FP64: 36 B record)
+REC_BYTES = {"fp32_offset": 24, "fp64": 36}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_step.hip", "device_common.h", "sim_layout.h"):
+        with open(os.path.join(ROOT, "paper_1104_3998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(precision):
+    """HBM traffic of k_main per particle-step from the committed rocprofv3 PMC summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_main_%s_large_pmc.md" % precision)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm bytes per particle-step:\s*([0-9.eE+-]+)", txt)
+    if not m_hash or not m_b or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def run_path(fs, torch, wls, precision, steps, warmup, graph_k=50, profile_steps=20,
+             tuning=None):
+    sim = fs.Simulation(wls, precision, tuning=tuning)
+    stream = sim.stream
+    sim.set_graph(graph_k)
+    sim.step(warmup)
+    sim.sync()
+    nd = len(wls)
+    ps0 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    wall = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.sync()
+    ps1 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
+    psteps = ps1 - ps0
+    # per-kernel durations: eager launches bracketed by HIP events on the same stream
+    sim.profile(True)
+    ps2 = ps1
+    sim.step(profile_steps)
+    sim.sync()
+    prof = sim.profile_read()
+    ps3 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
+    sim.profile(False)
+    diag = [sim.diagnostics(d) for d in range(nd)]
+    out = {
+        "value": psteps / (ms / 1e3),
+        "ms_per_step": ms / steps,
+        "wall_s": wall,
+        "particle_steps": psteps,
+        "particles_end": int(sum(sum(g.n_particles) for g in diag)),
+        "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
+        "profile_particle_steps": ps3 - ps2,
+        "profile_steps": profile_steps,
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(wl, steps):
+    import oracle
+    orc = oracle.Oracle(wl)
+    orc.load()
+    n0 = orc.count(0) + orc.count(1)
+    t0 = time.perf_counter()
+    tot = 0
+    for _ in range(steps):
+        tot += orc.count(0) + orc.count(1)
+        orc.step(1)
+    dt = time.perf_counter() - t0
+    return {"value": tot / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "large single discharge at full size (%d particles), %d oracle steps "
+                      "after the load, single-threaded C, FP64" % (n0, steps),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--skip-paths", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--path-steps", type=int, default=400)
+    ap.add_argument("--batched-scale", type=float, default=1.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs a discharge (or a batch of "
+              "discharges) on a single MI355X; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1104_3998_amd as fs
+    import workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    large = workloads.large_c3()
+    print("bench: FP32 cell+offset, large discharge, %d steps" % args.steps, file=sys.stderr,
+          flush=True)
+    head = run_path(fs, torch, large, "fp32_offset", args.steps, args.warmup)
+    paths = {}
+    if not args.skip_paths:
+        print("bench: FP64, large discharge", file=sys.stderr, flush=True)
+        r64 = run_path(fs, torch, large, "fp64", args.path_steps, args.warmup)
+        paths["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
+                         "steps": args.path_steps, "kernel_ms": r64["kernel_ms"]}
+        print("bench: batched scan", file=sys.stderr, flush=True)
+        batch = workloads.batched_c4(scale=args.batched_scale)
+        rb = run_path(fs, torch, batch, "fp32_offset", args.path_steps, args.warmup)
+        paths["batched"] = {"value": rb["value"], "ms_per_step": rb["ms_per_step"],
+                            "steps": args.path_steps, "discharges": len(batch),
+                            "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"]}
+    # roofline of the dominant kernel (k_main), FP32 path
+    kmain_ms = head["kernel_ms"]["main"]
+    ps_per_launch = head["profile_particle_steps"] / head["profile_steps"]
+    alg_bytes = 2 * REC_BYTES["fp32_offset"] * ps_per_launch
+    achieved = alg_bytes / (kmain_ms / 1e3) / 1e9
+    traffic = read_traffic("fp32_offset")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": "k_main",
+            "alg_bytes_per_launch": alg_bytes,
+            "traffic": traffic * ps_per_launch if traffic is not None else None}
+    cpu = None
+    if not args.skip_cpu:
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(large, args.cpu_steps)
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Philox-drawn Maxwellian load, no dataset)",
+        "config": {"workload": "large single discharge: 4096 cells (20 cm), 1e7 electrons + "
+                               "1e7 ions, Te 2 eV, 300 V at 13.56 MHz, 5 Pa Ar-like MCC, "
+                               "sort every step, FP32 cell+offset with FP64 Poisson",
+                   "particles": 20_000_000, "n_cells": 4096, "graph_steps": 50},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paths": dict({"fp32_offset": {"value": head["value"], "ms_per_step": head["ms_per_step"],
+                                       "kernel_ms": head["kernel_ms"]}}, **paths),
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -772,6 +772,9 @@ int orc_set_particles(orc_sim* s, int sp, int64_t n, const double* x, const doub
     memcpy(s->vy[sp], vy, (size_t)n * sizeof(double));
     memcpy(s->vz[sp], vz, (size_t)n * sizeof(double));
     memcpy(s->id[sp], id, (size_t)n * sizeof(uint32_t));
+    /* the node weights always describe the particles held */
+    memset(s->w[sp], 0, sizeof(double) * (size_t)s->n_nodes);
+    orc_deposit(s->p.periodic, s->p.n_cells, n, s->x[sp], s->w[sp]);
     return ORC_OK;
 }
 

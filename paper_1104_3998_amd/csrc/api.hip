@@ -1,0 +1,809 @@
+// api.hip -- the C ABI of libfspic (include/fspic.h): configuration checks, the carve-up
+// of the caller's workspace, the launch sequence of a step (eager or replayed from a
+// captured HIP graph), state upload/download and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_common.h"
+
+using namespace fspic;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kPhases = 6;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bump allocator over the workspace; with base == nullptr it only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (count ? count : 1);
+    return p;
+  }
+};
+
+struct Plan {
+  std::vector<pic_config> cfg;
+  std::vector<pic_derived> der;
+  std::vector<TileChoice> tiles;  // 2 per discharge
+  std::vector<SpeciesDev> sp;
+  std::vector<DischargeDev> ds;
+  std::vector<int2> tile_table;
+  SimDev sim{};
+  SimDev* d_sim = nullptr;
+  SpeciesDev* d_sp = nullptr;
+  DischargeDev* d_ds = nullptr;
+  int2* d_tt = nullptr;
+  LaunchInfo li{};
+  size_t bytes = 0;
+};
+
+int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* why) {
+  if (!cfgs || n < 1) {
+    *why = "need at least one configuration";
+    return PIC_ERR_ARG;
+  }
+  pl->cfg.assign(cfgs, cfgs + n);
+  pl->der.resize(n);
+  pl->tiles.resize(2 * n);
+  for (int d = 0; d < n; ++d) {
+    std::string w;
+    const int rc = validate_config(cfgs[d], &w);
+    if (rc != PIC_OK) {
+      *why = "discharge " + std::to_string(d) + ": " + w;
+      return rc;
+    }
+    if (cfgs[d].precision != cfgs[0].precision) {
+      *why = "all discharges of a simulation must use the same precision";
+      return PIC_ERR_ARG;
+    }
+    derive(cfgs[d], &pl->der[d]);
+    choose_tiles(cfgs[d], &pl->tiles[2 * d]);
+  }
+  const bool fp32 = cfgs[0].precision == PIC_FP32_OFFSET;
+  const size_t rs = fp32 ? 4 : 8;  // bytes of a real
+  Carver cv{ws};
+  pl->sp.assign(2 * n, SpeciesDev{});
+  pl->ds.assign(n, DischargeDev{});
+  pl->tile_table.clear();
+  int max_nodes = 0, max_cap = 0, max_cells = 0;
+  for (int d = 0; d < n; ++d) {
+    const pic_config& c = cfgs[d];
+    const pic_derived& k = pl->der[d];
+    const int N = static_cast<int>(c.n_cells);
+    const int nn = c.periodic ? N : N + 1;
+    max_nodes = std::max(max_nodes, nn);
+    max_cells = std::max(max_cells, N);
+    DischargeDev& D = pl->ds[d];
+    D.n_cells = N;
+    D.periodic = static_cast<int>(c.periodic);
+    D.n_nodes = nn;
+    D.spec0 = 2 * d;
+    for (int s = 0; s < 2; ++s) {
+      D.w[s] = cv.take<double>(nn);
+      D.acc_w[s] = cv.take<double>(nn);
+    }
+    D.phi = cv.take<double>(nn);
+    D.E64 = cv.take<double>(nn);
+    D.E32 = cv.take<float>(nn);
+    D.acc_phi = cv.take<double>(nn);
+    D.scratch = cv.take<double>(nn);
+    D.acc_count = cv.take<unsigned long long>(1);
+    D.eedf_samples = cv.take<unsigned long long>(1);
+    D.eedf_bins = static_cast<int>(c.eedf_bins);
+    D.eedf = cv.take<unsigned long long>(c.eedf_bins + 1);
+    D.diag_every = static_cast<int>(c.diag_every);
+    D.eedf_inv_width = c.eedf_bins > 0 ? static_cast<double>(c.eedf_bins) / c.eedf_max_ev : 0.0;
+    D.vhat_amp = k.vhat_amp;
+    D.phase_per_step = k.drive_phase_per_step;
+    D.avg_start = static_cast<int64_t>(c.avg_start_step);
+    for (int s = 0; s < 2; ++s) {
+      SpeciesDev& S = pl->sp[2 * d + s];
+      const TileChoice& tc = pl->tiles[2 * d + s];
+      const uint32_t cap = static_cast<uint32_t>(s == 0 ? c.capacity_e : c.capacity_i);
+      max_cap = std::max(max_cap, static_cast<int>(cap));
+      S.ds = d;
+      S.sp = s;
+      S.n_cells = N;
+      S.periodic = static_cast<int>(c.periodic);
+      S.C = tc.C;
+      S.D = tc.D;
+      S.W = tc.W;
+      S.n_tiles = tc.n_tiles;
+      S.n_tail = tc.n_tail;
+      S.n_nodes = nn;
+      S.cap = cap;
+      S.far_cap = c.far_capacity > 0 ? c.far_capacity : std::max<uint32_t>(65536u, cap / 8u);
+      for (int b = 0; b < 2; ++b) {
+        if (fp32) {
+          S.fld[b][F32_CELL] = cv.take<int>(cap);
+          S.fld[b][F32_OFF] = cv.take<float>(cap);
+        } else {
+          S.fld[b][F64_X] = cv.take<double>(cap);
+          S.fld[b][1] = nullptr;
+        }
+        for (int f = F_VX; f <= F_VZ; ++f) S.fld[b][f] = cv.take<char>(rs * cap);
+        S.fld[b][F_ID] = cv.take<uint32_t>(cap);
+      }
+      if (s == 0) {
+        for (int b = 0; b < 2; ++b) {
+          if (fp32) {
+            S.stage[b][F32_CELL] = cv.take<int>(cap);
+            S.stage[b][F32_OFF] = cv.take<float>(cap);
+          } else {
+            S.stage[b][F64_X] = cv.take<double>(cap);
+            S.stage[b][1] = nullptr;
+          }
+          for (int f = F_VX; f <= F_VZ; ++f) S.stage[b][f] = cv.take<char>(rs * cap);
+          S.stage[b][F_ID] = nullptr;
+        }
+      }
+      S.n_total = cv.take<uint32_t>(2);
+      S.n_sorted = cv.take<uint32_t>(2);
+      S.next_id = cv.take<uint32_t>(1);
+      S.cell_start = cv.take<uint32_t>(2 * (N + 1));
+      S.hist = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * tc.W);
+      S.tilerel = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * tc.W);
+      S.partial = cv.take<char>(rs * static_cast<size_t>(tc.n_tiles) * (tc.W + 1));
+      S.far_w = cv.take<double>(nn);
+      S.far_count = cv.take<uint32_t>(1);
+      S.far_list = cv.take<uint4>(S.far_cap);
+      S.far_grouped = cv.take<uint4>(S.far_cap);
+      S.far_cell_cnt = cv.take<uint32_t>(N);
+      S.far_fill = cv.take<uint32_t>(N);
+      S.far_base = cv.take<uint32_t>(N);
+      S.base = cv.take<uint32_t>(N);
+      S.far_dest = cv.take<uint32_t>(cap);
+      const int ntt = tc.n_tiles + tc.n_tail;
+      S.birth_cnt = cv.take<uint32_t>(ntt);
+      S.tile_first = cv.take<uint32_t>(ntt);
+      S.birth_base = cv.take<uint32_t>(ntt + 1);
+      S.absorbed = cv.take<unsigned long long>(2);
+      S.absorbed_energy = cv.take<double>(2);
+      S.births = cv.take<unsigned long long>(1);
+      S.collisions = cv.take<unsigned long long>(3);
+      S.ke_sum = cv.take<double>(4);
+      S.psteps = cv.take<unsigned long long>(1);
+      S.kappa = k.kappa[s];
+      S.kappa_f = static_cast<float>(k.kappa[s]);
+      S.t0 = k.t0[s];
+      S.energy_c = k.energy_c[s];
+      S.vunit = k.vunit;
+      S.n_gas = k.n_gas;
+      S.nu0 = k.nu0[s];
+      S.vth_gas = k.vth_gas;
+      S.mass_ratio = electron_mass() / ion_mass(c);
+      S.key0 = c.seed;
+      S.key1 = 2u * c.discharge_index + static_cast<uint32_t>(s);
+      S.xsec = static_cast<int>(c.xsec_model);
+      S.sigma_const = c.sigma_const_m2;
+      S.n_init = static_cast<uint32_t>(s == 0 ? c.n_e0 : c.n_i0);
+      S.load_kind = static_cast<int>(c.load_kind);
+      S.lang_mode = static_cast<int>(c.langmuir_mode);
+      S.vth = k.vth[s];
+      S.lang_amp = c.langmuir_amp_cells;
+      S.tile_base = static_cast<int>(pl->tile_table.size());
+      for (int t = 0; t < tc.n_tiles; ++t) pl->tile_table.push_back(make_int2(2 * d + s, t));
+      S.tail_base = static_cast<int>(pl->tile_table.size());
+      for (int j = 0; j < tc.n_tail; ++j)
+        pl->tile_table.push_back(make_int2(2 * d + s, tc.n_tiles + j));
+    }
+  }
+  const int n_gtiles = 256;
+  for (int i = 0; i < 2 * n; ++i)
+    pl->sp[i].gsort_hist = cv.take<uint32_t>(static_cast<size_t>(n_gtiles) * pl->sp[i].n_cells);
+  pl->sim.step = cv.take<unsigned long long>(1);
+  pl->sim.error = cv.take<uint32_t>(1);
+  pl->sim.fin_count = cv.take<uint32_t>(1);
+  pl->sim.n_ds = n;
+  pl->sim.n_spec = 2 * n;
+  pl->sim.total_tiles = static_cast<int>(pl->tile_table.size());
+  pl->sim.max_nodes = max_nodes;
+  pl->d_ds = cv.take<DischargeDev>(n);
+  pl->d_sp = cv.take<SpeciesDev>(2 * n);
+  pl->d_tt = cv.take<int2>(pl->tile_table.size());
+  pl->d_sim = cv.take<SimDev>(1);
+  pl->sim.ds = pl->d_ds;
+  pl->sim.sp = pl->d_sp;
+  pl->sim.tile_table = pl->d_tt;
+  pl->bytes = align_up(cv.off, 256);
+  LaunchInfo& li = pl->li;
+  li.n_ds = n;
+  li.n_spec = 2 * n;
+  li.total_tiles = pl->sim.total_tiles;
+  li.max_nodes = max_nodes;
+  li.max_cap = max_cap;
+  li.n_gtiles = n_gtiles;
+  li.max_cells = max_cells;
+  li.fp32 = fp32;
+  return PIC_OK;
+}
+
+}  // namespace
+
+struct pic_sim {
+  Plan pl;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  std::string err;
+  uint32_t sticky = 0;
+  // graph replay
+  uint32_t graph_k = 0;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  // profiling
+  bool prof = false;
+  hipEvent_t ev[kPhases + 1] = {};
+  double ms[kPhases] = {};
+  uint64_t cnt[kPhases] = {};
+};
+
+#define HIPCHECK(sim, expr)                                                   \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      (sim)->err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+      return PIC_ERR_DEVICE;                                                  \
+    }                                                                         \
+  } while (0)
+
+static int launch_check(pic_sim* sim, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    sim->err = std::string(what) + ": " + hipGetErrorString(e);
+    return PIC_ERR_DEVICE;
+  }
+  return PIC_OK;
+}
+
+static int map_error_bits(uint32_t bits) {
+  if (bits & kErrIdOverflow) return PIC_ERR_ID_OVERFLOW;
+  if (bits & (kErrCapacity | kErrFarOverflow | kErrFarGroup)) return PIC_ERR_CAPACITY;
+  if (bits & kErrState) return PIC_ERR_NONFINITE;
+  return PIC_OK;
+}
+
+static const char* error_text(uint32_t bits) {
+  if (bits & kErrIdOverflow) return "particle ids exhausted (2^32 - 1)";
+  if (bits & kErrCapacity) return "births did not fit the particle capacity";
+  if (bits & kErrFarOverflow) return "far-mover list overflow (raise far_capacity / window)";
+  if (bits & kErrFarGroup) return "too many far movers into one cell (raise window)";
+  if (bits & kErrState) return "invalid particle position or index refused";
+  return "";
+}
+
+extern "C" int pic_workspace_bytes(const pic_config* cfgs, int n, size_t* bytes) {
+  if (!bytes) return PIC_ERR_ARG;
+  Plan pl;
+  std::string why;
+  const int rc = build_plan(cfgs, n, nullptr, &pl, &why);
+  if (rc != PIC_OK) {
+    g_init_error = why;
+    return rc;
+  }
+  *bytes = pl.bytes;
+  return PIC_OK;
+}
+
+extern "C" int pic_derive(const pic_config* cfg, pic_derived* out) {
+  if (!cfg || !out) return PIC_ERR_ARG;
+  std::string why;
+  const int rc = validate_config(*cfg, &why);
+  if (rc != PIC_OK) {
+    g_init_error = why;
+    return rc;
+  }
+  return derive(*cfg, out);
+}
+
+static int step_once(pic_sim* sim, hipStream_t st) {
+  const LaunchInfo& li = sim->pl.li;
+  const SimDev* d = sim->pl.d_sim;
+  if (!sim->prof) {
+    launch_combine(li, d, st);
+    launch_solve(li, d, 0, st);
+    launch_hist(li, d, st);
+    launch_scan(li, d, st);
+    launch_main(li, d, st);
+    launch_finalize(li, d, st);
+    return launch_check(sim, "step launch");
+  }
+  HIPCHECK(sim, hipEventRecord(sim->ev[0], st));
+  launch_combine(li, d, st);
+  HIPCHECK(sim, hipEventRecord(sim->ev[1], st));
+  launch_solve(li, d, 0, st);
+  HIPCHECK(sim, hipEventRecord(sim->ev[2], st));
+  launch_hist(li, d, st);
+  HIPCHECK(sim, hipEventRecord(sim->ev[3], st));
+  launch_scan(li, d, st);
+  HIPCHECK(sim, hipEventRecord(sim->ev[4], st));
+  launch_main(li, d, st);
+  HIPCHECK(sim, hipEventRecord(sim->ev[5], st));
+  launch_finalize(li, d, st);
+  HIPCHECK(sim, hipEventRecord(sim->ev[6], st));
+  int rc = launch_check(sim, "step launch");
+  if (rc != PIC_OK) return rc;
+  HIPCHECK(sim, hipEventSynchronize(sim->ev[6]));
+  for (int p = 0; p < kPhases; ++p) {
+    float ms = 0.0f;
+    HIPCHECK(sim, hipEventElapsedTime(&ms, sim->ev[p], sim->ev[p + 1]));
+    sim->ms[p] += ms;
+    sim->cnt[p] += 1;
+  }
+  return PIC_OK;
+}
+
+extern "C" int pic_init(const pic_config* cfgs, int n, void* d_workspace, size_t bytes,
+                        void* hip_stream, pic_sim** out) {
+  if (!out) return PIC_ERR_ARG;
+  *out = nullptr;
+  pic_sim* sim = new pic_sim();
+  std::string why;
+  int rc = build_plan(cfgs, n, static_cast<char*>(d_workspace), &sim->pl, &why);
+  if (rc == PIC_OK && !d_workspace) {
+    why = "workspace pointer is null";
+    rc = PIC_ERR_ARG;
+  }
+  if (rc == PIC_OK && bytes < sim->pl.bytes) {
+    why = "workspace of " + std::to_string(bytes) + " bytes, need " +
+          std::to_string(sim->pl.bytes);
+    rc = PIC_ERR_WORKSPACE;
+  }
+  if (rc == PIC_OK && (reinterpret_cast<uintptr_t>(d_workspace) & 255u)) {
+    why = "workspace must be 256-byte aligned";
+    rc = PIC_ERR_ARG;
+  }
+  if (rc != PIC_OK) {
+    g_init_error = why;
+    delete sim;
+    return rc;
+  }
+  sim->ws = static_cast<char*>(d_workspace);
+  sim->stream = static_cast<hipStream_t>(hip_stream);
+  Plan& pl = sim->pl;
+  hipStream_t st = sim->stream;
+  auto fail = [&](int code) {
+    g_init_error = sim->err;
+    delete sim;
+    return code;
+  };
+#define INITCHECK(expr)                                                     \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      sim->err = std::string(#expr) + ": " + hipGetErrorString(e_);         \
+      return fail(PIC_ERR_DEVICE);                                          \
+    }                                                                       \
+  } while (0)
+  INITCHECK(hipMemsetAsync(sim->ws, 0, pl.bytes, st));
+  INITCHECK(hipMemcpyAsync(pl.d_ds, pl.ds.data(), sizeof(DischargeDev) * pl.ds.size(),
+                           hipMemcpyHostToDevice, st));
+  INITCHECK(hipMemcpyAsync(pl.d_sp, pl.sp.data(), sizeof(SpeciesDev) * pl.sp.size(),
+                           hipMemcpyHostToDevice, st));
+  INITCHECK(hipMemcpyAsync(pl.d_tt, pl.tile_table.data(), sizeof(int2) * pl.tile_table.size(),
+                           hipMemcpyHostToDevice, st));
+  INITCHECK(hipMemcpyAsync(pl.d_sim, &pl.sim, sizeof(SimDev), hipMemcpyHostToDevice, st));
+  for (const SpeciesDev& S : pl.sp)
+    INITCHECK(hipMemcpyAsync(S.next_id, &S.n_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  // load into buffer 1 (n_total[1] = n_init), sort into buffer 0
+  for (const SpeciesDev& S : pl.sp)
+    INITCHECK(hipMemcpyAsync(S.n_total + 1, &S.n_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  launch_load(pl.li, pl.d_sim, 1, st);
+  launch_general_sort(pl.li, pl.d_sim, 1, 0, st);
+  launch_deposit_tiles(pl.li, pl.d_sim, -1, st);
+  launch_combine(pl.li, pl.d_sim, st);
+  launch_solve(pl.li, pl.d_sim, 1, st);
+  launch_halfstep(pl.li, pl.d_sim, st);
+  if (launch_check(sim, "init launch") != PIC_OK) return fail(PIC_ERR_DEVICE);
+  INITCHECK(hipStreamSynchronize(st));
+  uint32_t bits = 0;
+  INITCHECK(hipMemcpy(&bits, pl.sim.error, sizeof(bits), hipMemcpyDeviceToHost));
+  if (bits) {
+    sim->err = error_text(bits);
+    return fail(map_error_bits(bits));
+  }
+#undef INITCHECK
+  *out = sim;
+  return PIC_OK;
+}
+
+static int ensure_graph(pic_sim* sim) {
+  if (sim->exec || sim->graph_k == 0) return PIC_OK;
+  if (!sim->cap_stream) HIPCHECK(sim, hipStreamCreateWithFlags(&sim->cap_stream, hipStreamNonBlocking));
+  HIPCHECK(sim, hipStreamBeginCapture(sim->cap_stream, hipStreamCaptureModeThreadLocal));
+  const bool prof = sim->prof;
+  sim->prof = false;
+  for (uint32_t k = 0; k < sim->graph_k; ++k) step_once(sim, sim->cap_stream);
+  sim->prof = prof;
+  hipGraph_t g = nullptr;
+  HIPCHECK(sim, hipStreamEndCapture(sim->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(&sim->exec, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    sim->exec = nullptr;
+    sim->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+    return PIC_ERR_DEVICE;
+  }
+  return PIC_OK;
+}
+
+extern "C" int pic_step(pic_sim* sim, uint32_t n_steps) {
+  if (!sim) return PIC_ERR_STATE;
+  uint32_t done = 0;
+  if (sim->graph_k > 0 && !sim->prof && n_steps >= sim->graph_k) {
+    const int rc = ensure_graph(sim);
+    if (rc != PIC_OK) return rc;
+    while (n_steps - done >= sim->graph_k) {
+      HIPCHECK(sim, hipGraphLaunch(sim->exec, sim->stream));
+      done += sim->graph_k;
+    }
+  }
+  for (; done < n_steps; ++done) {
+    const int rc = step_once(sim, sim->stream);
+    if (rc != PIC_OK) return rc;
+  }
+  return PIC_OK;
+}
+
+extern "C" int pic_set_graph(pic_sim* sim, uint32_t k) {
+  if (!sim) return PIC_ERR_STATE;
+  if (sim->exec) {
+    hipGraphExecDestroy(sim->exec);
+    sim->exec = nullptr;
+  }
+  sim->graph_k = k;
+  return PIC_OK;
+}
+
+extern "C" int pic_sync(pic_sim* sim) {
+  if (!sim) return PIC_ERR_STATE;
+  HIPCHECK(sim, hipStreamSynchronize(sim->stream));
+  uint32_t bits = 0;
+  HIPCHECK(sim, hipMemcpy(&bits, sim->pl.sim.error, sizeof(bits), hipMemcpyDeviceToHost));
+  sim->sticky |= bits;
+  if (sim->sticky) {
+    sim->err = error_text(sim->sticky);
+    return map_error_bits(sim->sticky);
+  }
+  return PIC_OK;
+}
+
+template <class T>
+static int d2h(pic_sim* sim, T* host, const T* dev, size_t count) {
+  if (count == 0) return PIC_OK;
+  HIPCHECK(sim, hipMemcpy(host, dev, sizeof(T) * count, hipMemcpyDeviceToHost));
+  return PIC_OK;
+}
+
+template <class T>
+static int h2d(pic_sim* sim, T* dev, const T* host, size_t count) {
+  if (count == 0) return PIC_OK;
+  HIPCHECK(sim, hipMemcpyAsync(dev, host, sizeof(T) * count, hipMemcpyHostToDevice, sim->stream));
+  HIPCHECK(sim, hipStreamSynchronize(sim->stream));
+  return PIC_OK;
+}
+
+static uint64_t device_step(pic_sim* sim, int* rc) {
+  unsigned long long st = 0;
+  *rc = d2h(sim, &st, sim->pl.sim.step, 1);
+  return st;
+}
+
+// Recomputes the node weights of the current particles (the combine of the next step).
+static int refresh_weights(pic_sim* sim) {
+  launch_combine(sim->pl.li, sim->pl.d_sim, sim->stream);
+  int rc = launch_check(sim, "combine");
+  if (rc != PIC_OK) return rc;
+  HIPCHECK(sim, hipStreamSynchronize(sim->stream));
+  return PIC_OK;
+}
+
+extern "C" int pic_grid(pic_sim* sim, int d, int what, double* out, size_t n_out) {
+  if (!sim) return PIC_ERR_STATE;
+  if (d < 0 || d >= sim->pl.li.n_ds || !out || what < 0 || what > 7) return PIC_ERR_ARG;
+  const DischargeDev& D = sim->pl.ds[d];
+  const size_t need = what == 7 ? static_cast<size_t>(D.eedf_bins) + 1 : D.n_nodes;
+  if (n_out < need) return PIC_ERR_ARG;
+  int rc = pic_sync(sim);
+  if (rc != PIC_OK && rc != PIC_ERR_CAPACITY && rc != PIC_ERR_ID_OVERFLOW &&
+      rc != PIC_ERR_NONFINITE)
+    return rc;
+  const int sticky = rc;
+  if (what <= 1) {
+    rc = refresh_weights(sim);
+    if (rc != PIC_OK) return rc;
+  }
+  switch (what) {
+    case 0: rc = d2h(sim, out, D.w[0], need); break;
+    case 1: rc = d2h(sim, out, D.w[1], need); break;
+    case 2: rc = d2h(sim, out, D.phi, need); break;
+    case 3: rc = d2h(sim, out, D.E64, need); break;
+    case 4: rc = d2h(sim, out, D.acc_w[0], need); break;
+    case 5: rc = d2h(sim, out, D.acc_w[1], need); break;
+    case 6: rc = d2h(sim, out, D.acc_phi, need); break;
+    default: {
+      std::vector<unsigned long long> tmp(need);
+      rc = d2h(sim, tmp.data(), D.eedf, need);
+      for (size_t i = 0; i < need; ++i) out[i] = static_cast<double>(tmp[i]);
+    }
+  }
+  return rc != PIC_OK ? rc : sticky;
+}
+
+extern "C" int pic_density(pic_sim* sim, int d, int quantity, int kind, double* out,
+                           size_t n_out) {
+  if (!sim) return PIC_ERR_STATE;
+  if (d < 0 || d >= sim->pl.li.n_ds || !out || quantity < 0 || quantity > 2 || kind < 0 ||
+      kind > 1)
+    return PIC_ERR_ARG;
+  const DischargeDev& D = sim->pl.ds[d];
+  const pic_derived& k = sim->pl.der[d];
+  const size_t nn = D.n_nodes;
+  if (n_out < nn) return PIC_ERR_ARG;
+  const int what = kind == 0 ? quantity : 4 + quantity;
+  int rc = pic_grid(sim, d, what, out, n_out);
+  if (rc != PIC_OK && rc != PIC_ERR_CAPACITY && rc != PIC_ERR_ID_OVERFLOW &&
+      rc != PIC_ERR_NONFINITE)
+    return rc;
+  double norm = 1.0;
+  if (kind == 1) {
+    unsigned long long c = 0;
+    const int r2 = d2h(sim, &c, D.acc_count, 1);
+    if (r2 != PIC_OK) return r2;
+    norm = c > 0 ? 1.0 / static_cast<double>(c) : 0.0;
+  }
+  if (quantity <= 1) {
+    const double f = norm * k.weight_per_area / k.dx;
+    for (size_t j = 0; j < nn; ++j) out[j] *= f;
+    if (!D.periodic) {
+      out[0] *= 2.0;
+      out[nn - 1] *= 2.0;
+    }
+  } else {
+    const double f = norm * k.phi_scale;
+    for (size_t j = 0; j < nn; ++j) out[j] *= f;
+  }
+  return rc;
+}
+
+extern "C" int pic_diagnostics(pic_sim* sim, int d, pic_diag* out) {
+  if (!sim) return PIC_ERR_STATE;
+  if (d < 0 || d >= sim->pl.li.n_ds || !out) return PIC_ERR_ARG;
+  const int sticky = pic_sync(sim);
+  if (sticky == PIC_ERR_DEVICE) return sticky;
+  std::memset(out, 0, sizeof(*out));
+  int rc;
+  const uint64_t step = device_step(sim, &rc);
+  if (rc != PIC_OK) return rc;
+  const int p = static_cast<int>(step & 1);
+  out->step = step;
+  const DischargeDev& D = sim->pl.ds[d];
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesDev& S = sim->pl.sp[2 * d + s];
+    uint32_t nt = 0, ns = 0, nid = 0;
+    unsigned long long ab[2] = {0, 0}, bi = 0, co[3] = {0, 0, 0};
+    double ae[2] = {0, 0};
+    if ((rc = d2h(sim, &nt, S.n_total + p, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, &ns, S.n_sorted + p, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, &nid, S.next_id, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, ab, S.absorbed, 2)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, ae, S.absorbed_energy, 2)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, &bi, S.births, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, co, S.collisions, 3)) != PIC_OK) return rc;
+    unsigned long long ps = 0;
+    if ((rc = d2h(sim, &ps, S.psteps, 1)) != PIC_OK) return rc;
+    out->particle_steps[s] = ps;
+    out->n_particles[s] = nt;
+    out->n_sorted[s] = ns;
+    out->next_id[s] = nid;
+    for (int w = 0; w < 2; ++w) {
+      out->absorbed[s][w] = ab[w];
+      out->absorbed_energy_ev[s][w] = ae[w];
+    }
+    out->births[s] = bi;
+    for (int c = 0; c < 3; ++c) out->collisions[s][c] = co[c];
+  }
+  unsigned long long ac = 0, es = 0;
+  if ((rc = d2h(sim, &ac, D.acc_count, 1)) != PIC_OK) return rc;
+  if ((rc = d2h(sim, &es, D.eedf_samples, 1)) != PIC_OK) return rc;
+  out->acc_count = ac;
+  out->eedf_samples = es;
+  double e0 = 0, en = 0;
+  if ((rc = d2h(sim, &e0, D.E64, 1)) != PIC_OK) return rc;
+  if ((rc = d2h(sim, &en, D.E64 + (D.n_nodes - 1), 1)) != PIC_OK) return rc;
+  out->surface_charge[0] = D.periodic ? 0.0 : e0;
+  out->surface_charge[1] = D.periodic ? 0.0 : -en;
+  out->error_flags = sim->sticky;
+  return sticky;
+}
+
+extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
+  if (!sim) return PIC_ERR_STATE;
+  if (d < 0 || d >= sim->pl.li.n_ds || !st) return PIC_ERR_ARG;
+  const int sticky = pic_sync(sim);
+  if (sticky == PIC_ERR_DEVICE) return sticky;
+  int rc;
+  const uint64_t step = device_step(sim, &rc);
+  if (rc != PIC_OK) return rc;
+  const int p = static_cast<int>(step & 1);
+  const bool fp32 = sim->pl.li.fp32;
+  if ((rc = refresh_weights(sim)) != PIC_OK) return rc;
+  const DischargeDev& D = sim->pl.ds[d];
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesDev& S = sim->pl.sp[2 * d + s];
+    uint32_t nt = 0, ns = 0, nid = 0;
+    if ((rc = d2h(sim, &nt, S.n_total + p, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, &ns, S.n_sorted + p, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, &nid, S.next_id, 1)) != PIC_OK) return rc;
+    st->n[s] = nt;
+    st->n_sorted[s] = ns;
+    st->next_id[s] = nid;
+    if (nt > st->capacity[s]) {
+      sim->err = "pic_get_state: host arrays smaller than the particle count";
+      return PIC_ERR_CAPACITY;
+    }
+    void* const* f = S.fld[p];
+    if (fp32) {
+      if (st->cell[s] && (rc = d2h(sim, st->cell[s], static_cast<const int32_t*>(f[F32_CELL]), nt))) return rc;
+      if (st->off[s] && (rc = d2h(sim, st->off[s], static_cast<const float*>(f[F32_OFF]), nt))) return rc;
+      if (st->vxf[s] && (rc = d2h(sim, st->vxf[s], static_cast<const float*>(f[F_VX]), nt))) return rc;
+      if (st->vyf[s] && (rc = d2h(sim, st->vyf[s], static_cast<const float*>(f[F_VY]), nt))) return rc;
+      if (st->vzf[s] && (rc = d2h(sim, st->vzf[s], static_cast<const float*>(f[F_VZ]), nt))) return rc;
+    } else {
+      if (st->x[s] && (rc = d2h(sim, st->x[s], static_cast<const double*>(f[F64_X]), nt))) return rc;
+      if (st->vx[s] && (rc = d2h(sim, st->vx[s], static_cast<const double*>(f[F_VX]), nt))) return rc;
+      if (st->vy[s] && (rc = d2h(sim, st->vy[s], static_cast<const double*>(f[F_VY]), nt))) return rc;
+      if (st->vz[s] && (rc = d2h(sim, st->vz[s], static_cast<const double*>(f[F_VZ]), nt))) return rc;
+    }
+    if (st->id[s] && (rc = d2h(sim, st->id[s], static_cast<const uint32_t*>(f[F_ID]), nt))) return rc;
+    if (st->w[s] && (rc = d2h(sim, st->w[s], D.w[s], D.n_nodes))) return rc;
+  }
+  st->step = step;
+  return sticky;
+}
+
+extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
+  if (!sim) return PIC_ERR_STATE;
+  if (d < 0 || d >= sim->pl.li.n_ds || !st) return PIC_ERR_ARG;
+  int rc = pic_sync(sim);
+  if (rc == PIC_ERR_DEVICE) return rc;
+  const uint64_t cur = device_step(sim, &rc);
+  if (rc != PIC_OK) return rc;
+  if (sim->pl.li.n_ds > 1 && st->step != cur) {
+    sim->err = "pic_set_state: in a batched simulation the step must stay the same";
+    return PIC_ERR_ARG;
+  }
+  const bool fp32 = sim->pl.li.fp32;
+  const DischargeDev& D = sim->pl.ds[d];
+  const int N = D.n_cells;
+  // validate on the host before anything is uploaded
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesDev& S = sim->pl.sp[2 * d + s];
+    const uint64_t n = st->n[s], ns = st->sort_all ? 0 : st->n_sorted[s];
+    if (n > S.cap || ns > n) {
+      sim->err = "pic_set_state: counts exceed capacity";
+      return PIC_ERR_ARG;
+    }
+    if (n && !st->id[s]) return PIC_ERR_ARG;
+    long prev = -1;
+    for (uint64_t i = 0; i < n; ++i) {
+      long c;
+      if (fp32) {
+        if (!st->cell[s] || !st->off[s] || !st->vxf[s] || !st->vyf[s] || !st->vzf[s]) return PIC_ERR_ARG;
+        const float o = st->off[s][i];
+        c = st->cell[s][i];
+        if (c < 0 || c >= N || !(o >= 0.0f && o < 1.0f)) {
+          sim->err = "pic_set_state: position outside the box";
+          return PIC_ERR_ARG;
+        }
+      } else {
+        if (!st->x[s] || !st->vx[s] || !st->vy[s] || !st->vz[s]) return PIC_ERR_ARG;
+        const double x = st->x[s][i];
+        if (!(x >= 0.0 && x < static_cast<double>(N))) {
+          sim->err = "pic_set_state: position outside the box";
+          return PIC_ERR_ARG;
+        }
+        c = static_cast<long>(std::floor(x));
+      }
+      if (i < ns) {
+        if (c < prev) {
+          sim->err = "pic_set_state: the first n_sorted particles are not ordered by cell";
+          return PIC_ERR_ARG;
+        }
+        prev = c;
+      }
+    }
+  }
+  // the step counter decides which buffer holds the state
+  unsigned long long stp = st->step;
+  if ((rc = h2d(sim, sim->pl.sim.step, &stp, 1)) != PIC_OK) return rc;
+  const int p = static_cast<int>(stp & 1);
+  const int up = st->sort_all ? p ^ 1 : p;
+  for (int s = 0; s < 2; ++s) {
+    const SpeciesDev& S = sim->pl.sp[2 * d + s];
+    const uint32_t n = static_cast<uint32_t>(st->n[s]);
+    const uint32_t ns = st->sort_all ? n : static_cast<uint32_t>(st->n_sorted[s]);
+    void* const* f = S.fld[up];
+    if (fp32) {
+      if ((rc = h2d(sim, static_cast<int32_t*>(f[F32_CELL]), st->cell[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<float*>(f[F32_OFF]), st->off[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<float*>(f[F_VX]), st->vxf[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<float*>(f[F_VY]), st->vyf[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<float*>(f[F_VZ]), st->vzf[s], n))) return rc;
+    } else {
+      if ((rc = h2d(sim, static_cast<double*>(f[F64_X]), st->x[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<double*>(f[F_VX]), st->vx[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<double*>(f[F_VY]), st->vy[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<double*>(f[F_VZ]), st->vz[s], n))) return rc;
+    }
+    if ((rc = h2d(sim, static_cast<uint32_t*>(f[F_ID]), st->id[s], n))) return rc;
+    const uint32_t cnt[2] = {n, ns};
+    if ((rc = h2d(sim, S.n_total + up, &cnt[0], 1))) return rc;
+    if ((rc = h2d(sim, S.n_sorted + up, &cnt[1], 1))) return rc;
+    const uint32_t nid = st->next_id[s];
+    if ((rc = h2d(sim, S.next_id, &nid, 1))) return rc;
+    HIPCHECK(sim, hipMemsetAsync(S.far_w, 0, sizeof(double) * S.n_nodes, sim->stream));
+  }
+  if (st->sort_all) {
+    // the general sort covers every species; keep the other discharges' buffers intact by
+    // sorting only when this is the only discharge
+    if (sim->pl.li.n_ds != 1) {
+      sim->err = "pic_set_state: sort_all is only available for a single discharge";
+      return PIC_ERR_ARG;
+    }
+    launch_general_sort(sim->pl.li, sim->pl.d_sim, up, p, sim->stream);
+  } else {
+    for (int s = 0; s < 2; ++s) launch_cell_start(sim->pl.li, sim->pl.d_sim, 2 * d + s, p, sim->stream);
+  }
+  launch_deposit_tiles(sim->pl.li, sim->pl.d_sim, d, sim->stream);
+  if ((rc = launch_check(sim, "set_state")) != PIC_OK) return rc;
+  HIPCHECK(sim, hipStreamSynchronize(sim->stream));
+  return PIC_OK;
+}
+
+extern "C" int pic_profile(pic_sim* sim, int enable) {
+  if (!sim) return PIC_ERR_STATE;
+  if (enable && !sim->ev[0])
+    for (int i = 0; i <= kPhases; ++i) HIPCHECK(sim, hipEventCreate(&sim->ev[i]));
+  sim->prof = enable != 0;
+  for (int i = 0; i < kPhases; ++i) {
+    sim->ms[i] = 0.0;
+    sim->cnt[i] = 0;
+  }
+  return PIC_OK;
+}
+
+extern "C" int pic_profile_read(pic_sim* sim, double* ms, uint64_t* launches, int n) {
+  if (!sim || !ms || !launches) return PIC_ERR_ARG;
+  for (int i = 0; i < n && i < kPhases; ++i) {
+    ms[i] = sim->ms[i];
+    launches[i] = sim->cnt[i];
+  }
+  return PIC_OK;
+}
+
+extern "C" void pic_free(pic_sim* sim) {
+  if (!sim) return;
+  if (sim->stream) hipStreamSynchronize(sim->stream);
+  if (sim->exec) hipGraphExecDestroy(sim->exec);
+  if (sim->cap_stream) hipStreamDestroy(sim->cap_stream);
+  for (int i = 0; i <= kPhases; ++i)
+    if (sim->ev[i]) hipEventDestroy(sim->ev[i]);
+  delete sim;
+}
+
+extern "C" const char* pic_last_error(const pic_sim* sim) {
+  return sim ? sim->err.c_str() : g_init_error.c_str();
+}

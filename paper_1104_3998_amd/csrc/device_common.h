@@ -1,0 +1,313 @@
+// device_common.h -- device-side building blocks of the PIC-MCC step kernels:
+// counter-based draws, the Ar-like cross sections, the leap-frog push of both particle
+// layouts, the collision kinematics, tile-window geometry and workgroup scans.
+//
+// Everything here is evaluated one IEEE operation at a time (the library is built with
+// -ffp-contract=off), so the push and the collision decisions come out identical in
+// every kernel that calls them.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sim_layout.h"
+
+namespace fspic {
+
+// ------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplications on the 4-word counter, the key advanced by a Weyl sequence between
+// rounds.  Stateless, keyed by (seed, 2 * discharge + species), counter (id, step, block,
+// tag): any thread can produce any particle's draw, unlike the per-thread xorshift
+// state of the paper's Sec. 3.8.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo_a = 0xD2511F53u * c0;
+    const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo_b = 0xCD9E8D57u * c2;
+    const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi_b ^ c1 ^ k0;
+    const uint32_t n2 = hi_a ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo_b;
+    c2 = n2;
+    c3 = lo_a;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// uniform in [0, 1) from 53 bits: all of a, the top 21 bits of b
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+  const uint64_t m = (static_cast<uint64_t>(a) << 21) | static_cast<uint64_t>(b >> 11);
+  return static_cast<double>(m) * (1.0 / 9007199254740992.0);
+}
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+__device__ __forceinline__ void normals64(uint4 b, double& z0, double& z1) {
+  const double ua = u53(b.x, b.y);
+  const double ub = u53(b.z, b.w);
+  const double r = sqrt(-2.0 * log(1.0 - ua));
+  const double th = kTwoPi * ub;
+  z0 = r * cos(th);
+  z1 = r * sin(th);
+}
+
+// isotropic unit vector, first component along the discharge axis
+__device__ __forceinline__ void direction64(uint4 b, double& n0, double& n1, double& n2) {
+  const double ua = u53(b.x, b.y);
+  const double ub = u53(b.z, b.w);
+  const double ct = 1.0 - 2.0 * ua;
+  const double st = sqrt(1.0 - ct * ct);
+  const double ph = kTwoPi * ub;
+  n0 = ct;
+  n1 = st * cos(ph);
+  n2 = st * sin(ph);
+}
+
+__device__ __forceinline__ void direction32(uint4 b, float& n0, float& n1, float& n2) {
+  const double ua = u53(b.x, b.y);
+  const double ub = u53(b.z, b.w);
+  const float ct = static_cast<float>(1.0 - 2.0 * ua);
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  const float ph = static_cast<float>(kTwoPi * ub);
+  float sn, cs;
+  sincosf(ph, &sn, &cs);
+  n0 = ct;
+  n1 = st * cs;
+  n2 = st * sn;
+}
+
+// ------------------------------------------------------------------------------------
+// Cross sections: synthetic Ar-like model standing in for the paper's analytic argon fits
+// (Sec. 3.8): electrons elastic / excitation (11.5 eV) / ionisation (15.8 eV), ions
+// isotropic / charge exchange; constant-sigma electron-elastic model; sigma in m^2.
+// ------------------------------------------------------------------------------------
+enum { XS_NONE = 0, XS_CONST_E_ELASTIC = 1, XS_AR_LIKE = 2 };
+constexpr double kExcEv = 11.5;
+constexpr double kIonEv = 15.8;
+
+__device__ __forceinline__ void xsec_electron(int model, double eps, double sc, double& el,
+                                              double& ex, double& iz) {
+  el = ex = iz = 0.0;
+  if (model == XS_CONST_E_ELASTIC) {
+    el = sc;
+    return;
+  }
+  if (model != XS_AR_LIKE) return;
+  const double xe = eps / 12.0;
+  el = 3e-19 * (xe + 0.05) / (1.0 + xe * xe);
+  if (eps > kExcEv) {
+    const double u = (eps - kExcEv) / 20.0;
+    ex = 2e-20 * (2.0 * u) / (1.0 + u * u);
+  }
+  if (eps > kIonEv) {
+    const double u = (eps - kIonEv) / 60.0;
+    iz = 3e-20 * (2.0 * u) / (1.0 + u * u);
+  }
+}
+
+__device__ __forceinline__ void xsec_ion(int model, double eps, double& is, double& cx) {
+  is = cx = 0.0;
+  if (model != XS_AR_LIKE) return;
+  is = 2e-19 * (1.0 + 2.0 / (1.0 + eps)) / (1.0 + eps / 100.0);
+  cx = 3e-19 * (1.0 + 1.0 / (1.0 + eps)) / (1.0 + eps / 1000.0);
+}
+
+// ------------------------------------------------------------------------------------
+// Leap-frog push with linear gather (Sec. 3.6) and the wall test (Sec. 2):
+// status 0 kept, 1 left the box at x < 0, 2 at x >= N, 3 not a finite position.
+// ------------------------------------------------------------------------------------
+// FP32 cell + offset: the update is made on the offset so its resolution does not
+// depend on the cell index.
+__device__ __forceinline__ int push32(int c, float f, float vx, float e0, float e1, float kf,
+                                      int N, int periodic, int& d, float& fo, float& vo) {
+  const float t = 1.0f - f;
+  const float a = t * e0;
+  const float b = f * e1;
+  const float ep = a + b;
+  const float dv = kf * ep;
+  const float v = vx + dv;
+  float fn = f + v;
+  const float kfl = floorf(fn);
+  vo = v;
+  if (!(fabsf(kfl) < 1.0e9f)) {
+    d = 0;
+    fo = 0.0f;
+    return 3;
+  }
+  int dd = c + static_cast<int>(kfl);
+  fn = fn - kfl;
+  if (fn >= 1.0f) {
+    fn = 0.0f;
+    dd += 1;
+  }
+  fo = fn;
+  if (periodic) {
+    dd %= N;
+    if (dd < 0) dd += N;
+    d = dd;
+    return 0;
+  }
+  d = dd;
+  if (dd < 0) return 1;
+  if (dd >= N) return 2;
+  return 0;
+}
+
+// FP64 absolute position.
+__device__ __forceinline__ int push64(double x, double vx, double e0, double e1, double kappa,
+                                      int N, int periodic, double& xo, double& vo, int& d) {
+  const double c = floor(x);
+  const double f = x - c;
+  const double ep = (1.0 - f) * e0 + f * e1;
+  const double v = vx + kappa * ep;
+  double xn = x + v;
+  vo = v;
+  const double dn = static_cast<double>(N);
+  if (!(fabs(xn) < 1.0e15)) {
+    xo = 0.0;
+    d = 0;
+    return 3;
+  }
+  if (periodic) {
+    if (xn < 0.0 || xn >= dn) {
+      const double k = floor(xn / dn);
+      xn = xn - k * dn;
+      for (int it = 0; it < 4 && xn < 0.0; ++it) xn += dn;
+      for (int it = 0; it < 4 && xn >= dn; ++it) xn -= dn;
+    }
+    xo = xn;
+    int dd = static_cast<int>(floor(xn));
+    if (dd >= N) dd = N - 1;
+    if (dd < 0) dd = 0;
+    d = dd;
+    return 0;
+  }
+  xo = xn;
+  if (xn < 0.0) {
+    d = -1;
+    return 1;
+  }
+  if (xn >= dn) {
+    d = N;
+    return 2;
+  }
+  d = static_cast<int>(floor(xn));
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------
+// Tile-window geometry.  Cell tile t of a species owns cells [tC, tC + C); its window
+// starts at cell tC - D.  A histogram window spans W = C + 2D cells, a deposit window
+// W + 1 nodes.  for_covering visits, in increasing tile index, every tile whose window
+// (of `span` slots) contains cell / node j, with j's slot in that window.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int floordiv(int a, int b) {
+  return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+template <class F>
+__device__ __forceinline__ void for_covering(const SpeciesDev& s, int j, int span, F&& f) {
+  const int C = s.C, D = s.D, n = s.n_tiles, N = s.n_cells;
+  const int thi = floordiv(j + D, C);
+  const int tlo = floordiv(j + D - span, C) + 1;
+  if (!s.periodic) {
+    const int a = tlo < 0 ? 0 : tlo;
+    const int b = thi > n - 1 ? n - 1 : thi;
+    for (int t = a; t <= b; ++t) f(t, j - t * C + D);
+    return;
+  }
+  auto slot = [&](int t) {
+    int k = (j - t * C + D) % N;
+    return k < 0 ? k + N : k;
+  };
+  if (tlo < 0) {
+    for (int t = 0; t <= thi; ++t) f(t, slot(t));
+    for (int t = tlo + n; t <= n - 1; ++t) f(t, slot(t));
+  } else if (thi > n - 1) {
+    for (int t = 0; t <= thi - n; ++t) f(t, slot(t));
+    for (int t = tlo; t <= n - 1; ++t) f(t, slot(t));
+  } else {
+    for (int t = tlo; t <= thi; ++t) f(t, slot(t));
+  }
+}
+
+// slot of cell d in the window of tile t, or -1 if outside [0, W)
+__device__ __forceinline__ int window_slot(const SpeciesDev& s, int t, int d) {
+  int k = d - (t * s.C - s.D);
+  if (s.periodic) {
+    k %= s.n_cells;
+    if (k < 0) k += s.n_cells;
+  }
+  return (k >= 0 && k < s.W) ? k : -1;
+}
+
+// ------------------------------------------------------------------------------------
+// Workgroup scans (fixed summation order, so results do not depend on scheduling).
+// ------------------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o, 64);
+    if (lane >= o) x = x + y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread over the workgroup; `lds` holds blockDim/64+1
+// entries.  Returns the exclusive prefix, writes the total.
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const T inc = wave_inclusive_scan(v);
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T r = T(0);
+    for (int i = 0; i < nw; ++i) {
+      const T t = lds[i];
+      lds[i] = r;
+      r = r + t;
+    }
+    lds[nw] = r;
+  }
+  __syncthreads();
+  const T ex = lds[w] + (inc - v);
+  total = lds[nw];
+  __syncthreads();
+  return ex;
+}
+
+// In-place exclusive scan of a[0..n) by one workgroup; returns the total.
+template <class T>
+__device__ T array_exclusive_scan(T* a, int n, T* lds) {
+  __threadfence();
+  __syncthreads();
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < n ? lo + per : n;
+  T sum = T(0);
+  for (int i = lo; i < hi; ++i) sum = sum + a[i];
+  T total;
+  T run = block_exclusive_scan(sum, lds, total);
+  for (int i = lo; i < hi; ++i) {
+    const T v = a[i];
+    a[i] = run;
+    run = run + v;
+  }
+  __threadfence();
+  __syncthreads();
+  return total;
+}
+
+}  // namespace fspic

@@ -1,0 +1,46 @@
+// host_common.h -- declarations shared by the host-side files of libfspic.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/fspic.h"
+#include "sim_layout.h"
+
+namespace fspic {
+
+struct TileChoice {
+  int C, D, W, n_tiles, n_tail;
+};
+
+int validate_config(const pic_config& c, std::string* why);
+int derive(const pic_config& c, pic_derived* k);
+void choose_tiles(const pic_config& c, TileChoice tc[2]);
+double electron_mass();
+double ion_mass(const pic_config& c);
+
+// Launch geometry the host needs beside the device descriptors.
+struct LaunchInfo {
+  int n_ds, n_spec, total_tiles, max_nodes, max_cap, n_gtiles, max_cells;
+  bool fp32;
+};
+
+// Step kernels (kernels_step.hip).  `sim` points at the SimDev copy in device memory.
+void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st);
+void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+
+// Set-up kernels (kernels_setup.hip).
+void launch_load(const LaunchInfo& li, const SimDev* sim, int dst_buf, hipStream_t st);
+void launch_general_sort(const LaunchInfo& li, const SimDev* sim, int src_buf, int dst_buf,
+                         hipStream_t st);
+void launch_cell_start(const LaunchInfo& li, const SimDev* sim, int spec, int buf,
+                       hipStream_t st);
+void launch_deposit_tiles(const LaunchInfo& li, const SimDev* sim, int ds_filter,
+                          hipStream_t st);
+void launch_halfstep(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+
+}  // namespace fspic

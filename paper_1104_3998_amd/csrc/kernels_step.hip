@@ -1,0 +1,902 @@
+// kernels_step.hip -- the kernels of one PIC-MCC step (Sec. 2 cycle), in launch order:
+//
+//   k_combine   node weights w_s = sum of the tile deposit windows + far/birth deposits
+//   k_solve     Poisson + field on the nodes (Sec. 3.5), one workgroup per discharge
+//   k_hist      per-tile LDS histogram of the post-push cells (sort pre-pass, Sec. 3.7)
+//   k_scan      per-(tile, cell) output offsets; far movers ranked (one workgroup per
+//               discharge and species)
+//   k_main      push + gather (Sec. 3.6), walls (Sec. 2), null-collision MCC (Sec. 3.8),
+//               stable scatter into the sorted output, LDS deposit (Sec. 3.4)
+//   k_finalize  births appended in parent order, counters, step advance
+//
+// A tile is the set of particles of C consecutive cells (the paper puts one sorting cell
+// per thread block, Sec. 3.2); the output of a tile's particles can only land within D
+// cells of its cells except for rare far movers, so the stable counting sort needs
+// only a (C + 2D)-slot histogram per tile.  No global float atomics are used on the
+// bulk path; far movers and births (a small fraction) add into a per-node FP64 array.
+#include <type_traits>
+
+#include "device_common.h"
+#include "host_common.h"
+
+namespace fspic {
+
+struct P32 {};
+struct P64 {};
+
+template <class P>
+struct Part;
+
+template <>
+struct Part<P32> {
+  using real = float;
+  int cell;
+  float off, vx, vy, vz;
+  uint32_t id;
+  __device__ __forceinline__ void load(void* const* f, uint32_t i) {
+    cell = static_cast<const int*>(f[F32_CELL])[i];
+    off = static_cast<const float*>(f[F32_OFF])[i];
+    vx = static_cast<const float*>(f[F_VX])[i];
+    vy = static_cast<const float*>(f[F_VY])[i];
+    vz = static_cast<const float*>(f[F_VZ])[i];
+    id = static_cast<const uint32_t*>(f[F_ID])[i];
+  }
+};
+
+template <>
+struct Part<P64> {
+  using real = double;
+  double x, vx, vy, vz;
+  uint32_t id;
+  __device__ __forceinline__ void load(void* const* f, uint32_t i) {
+    x = static_cast<const double*>(f[F64_X])[i];
+    vx = static_cast<const double*>(f[F_VX])[i];
+    vy = static_cast<const double*>(f[F_VY])[i];
+    vz = static_cast<const double*>(f[F_VZ])[i];
+    id = static_cast<const uint32_t*>(f[F_ID])[i];
+  }
+};
+
+// position of a particle after the push: cell d and offset (FP32) or absolute x (FP64)
+template <class P>
+__device__ __forceinline__ void store_record(void* const* f, uint32_t i, int d,
+                                             typename Part<P>::real pos,
+                                             typename Part<P>::real vx,
+                                             typename Part<P>::real vy,
+                                             typename Part<P>::real vz, uint32_t id) {
+  if constexpr (std::is_same<P, P32>::value) {
+    static_cast<int*>(f[F32_CELL])[i] = d;
+    static_cast<float*>(f[F32_OFF])[i] = pos;
+  } else {
+    static_cast<double*>(f[F64_X])[i] = pos;
+  }
+  using real = typename Part<P>::real;
+  static_cast<real*>(f[F_VX])[i] = vx;
+  static_cast<real*>(f[F_VY])[i] = vy;
+  static_cast<real*>(f[F_VZ])[i] = vz;
+  static_cast<uint32_t*>(f[F_ID])[i] = id;
+}
+
+struct TileRange {
+  uint32_t lo, hi;
+  int c0;
+  bool tail;
+};
+
+__device__ __forceinline__ TileRange tile_range(const SpeciesDev& s, int t, int p) {
+  TileRange r;
+  r.tail = t >= s.n_tiles;
+  if (!r.tail) {
+    r.c0 = t * s.C;
+    const int c1 = min(r.c0 + s.C, s.n_cells);
+    const uint32_t* cs = s.cell_start + p * (s.n_cells + 1);
+    r.lo = cs[r.c0];
+    r.hi = cs[c1];
+  } else {
+    r.c0 = 0;
+    const uint32_t ns = s.n_sorted[p], nt = s.n_total[p];
+    const uint32_t ntail = nt > ns ? nt - ns : 0u;
+    const uint32_t per = (ntail + s.n_tail - 1) / s.n_tail;
+    const uint32_t j = static_cast<uint32_t>(t - s.n_tiles);
+    r.lo = min(nt, ns + j * per);
+    r.hi = min(nt, r.lo + per);
+  }
+  if (r.hi < r.lo) r.hi = r.lo;
+  return r;
+}
+
+// Loads the field of the tile's nodes [c0, c0 + C] into LDS (node index wrapped when
+// periodic).  Tail tiles read the global array instead.
+template <class real>
+__device__ __forceinline__ void load_field_window(const SpeciesDev& s, const real* E,
+                                                  const TileRange& r, real* Elds) {
+  if (r.tail) return;
+  for (int k = threadIdx.x; k <= s.C; k += blockDim.x) {
+    int n = r.c0 + k;
+    if (s.periodic) n %= s.n_cells;
+    if (n > s.n_nodes - 1) n = s.n_nodes - 1;
+    Elds[k] = E[n];
+  }
+}
+
+template <class real>
+__device__ __forceinline__ real field_at(const SpeciesDev& s, const real* E, const real* Elds,
+                                         const TileRange& r, int node) {
+  int k = node - r.c0;
+  if (!r.tail && k >= 0 && k <= s.C) return Elds[k];
+  if (s.periodic && node >= s.n_cells) node -= s.n_cells;
+  return E[node];
+}
+
+// Push one particle: returns status (0 kept, 1/2 wall, 3 invalid), the destination cell
+// d, the new position word (offset or x) and the new v_x.
+template <class P>
+__device__ __forceinline__ int push_particle(const SpeciesDev& s, const DischargeDev& dd,
+                                             const typename Part<P>::real* Elds,
+                                             const TileRange& r, const Part<P>& q, int& d,
+                                             typename Part<P>::real& pos,
+                                             typename Part<P>::real& vxn) {
+  if constexpr (std::is_same<P, P32>::value) {
+    const int c = q.cell;
+    if (c < 0 || c >= s.n_cells) {
+      d = 0;
+      pos = 0.0f;
+      vxn = q.vx;
+      return 3;
+    }
+    const float e0 = field_at<float>(s, dd.E32, Elds, r, c);
+    const float e1 = field_at<float>(s, dd.E32, Elds, r, c + 1);
+    return push32(c, q.off, q.vx, e0, e1, s.kappa_f, s.n_cells, s.periodic, d, pos, vxn);
+  } else {
+    if (!(q.x >= 0.0 && q.x < static_cast<double>(s.n_cells))) {
+      d = 0;
+      pos = 0.0;
+      vxn = q.vx;
+      return 3;
+    }
+    const int c = static_cast<int>(floor(q.x));
+    const double e0 = field_at<double>(s, dd.E64, Elds, r, c);
+    const double e1 = field_at<double>(s, dd.E64, Elds, r, c + 1);
+    return push64(q.x, q.vx, e0, e1, s.kappa, s.n_cells, s.periodic, pos, vxn, d);
+  }
+}
+
+__device__ __forceinline__ bool diag_step(const DischargeDev& dd, unsigned long long step) {
+  if (dd.eedf_bins <= 0 || dd.diag_every <= 0) return false;
+  const long long st = static_cast<long long>(step);
+  if (st < dd.avg_start) return false;
+  return ((st - dd.avg_start) % dd.diag_every) == 0;
+}
+
+// ====================================================================================
+// k_combine: w_s[j] = sum over the tiles whose deposit window holds node j (fixed tile
+// order) + the far / birth deposits.  Grid: (node blocks, species).
+// ====================================================================================
+template <class real>
+__global__ __launch_bounds__(256) void k_combine(const SimDev* __restrict__ simp) {
+  const SimDev& sim = *simp;
+  const SpeciesDev& s = sim.sp[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s.n_nodes) return;
+  const real* part = static_cast<const real*>(s.partial);
+  const int span = s.W + 1;
+  double sum = 0.0;
+  for_covering(s, j, span, [&](int t, int k) {
+    sum += static_cast<double>(part[static_cast<size_t>(t) * span + k]);
+  });
+  sum += s.far_w[j];
+  sim.ds[s.ds].w[s.sp][j] = sum;
+}
+
+// ====================================================================================
+// k_solve: one workgroup per discharge.  The finite-difference Poisson system of eq.
+// poisson_normalized (Sec. 3.5) with Phi_0 = V(t_n), Phi_N = 0 (or periodic, mean charge
+// removed, Phi_0 = 0) is solved exactly as the paper's tridiagonal system, but in the
+// parallel form of its two recurrences: the slopes s_j = Phi_{j+1} - Phi_j obey
+// s_j = s_0 - R_j with R_j = sum_{k=1..j} rho_k, s_0 fixed by the two end potentials;
+// Phi is the running sum of s.  E_j = -(s_{j-1} + s_j)/2 inside; at an electrode Gauss's
+// law over the half cell: E_0 = -s_0 - rho_0, E_N = -s_{N-1} + rho_N.
+// ====================================================================================
+__global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ simp,
+                                                    int init_mode) {
+  const SimDev& sim = *simp;
+  const DischargeDev& dd = sim.ds[blockIdx.x];
+  __shared__ double lds_d[kSolveWG / 64 + 1];
+  const unsigned long long step = init_mode ? 0ull : *sim.step;
+  const int N = dd.n_cells;
+  const int nn = dd.n_nodes;
+  const double* we = dd.w[0];
+  const double* wi = dd.w[1];
+  double* phi = dd.phi;  // holds R_j, then Phi
+  double* E = dd.E64;    // holds s_j, then E
+  const int per = (N + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per;
+  const int hi = min(lo + per, N);
+  double total;
+  // mean charge (periodic only)
+  double mean = 0.0;
+  if (dd.periodic) {
+    double part = 0.0;
+    for (int j = lo; j < hi; ++j) part += wi[j] - we[j];
+    block_exclusive_scan(part, lds_d, total);
+    mean = total / static_cast<double>(N);
+  }
+  // R_j = sum_{k=1..j} (rho_k - mean), j = 0..N-1
+  {
+    double part = 0.0;
+    for (int j = lo; j < hi; ++j)
+      if (j >= 1) part += (wi[j] - we[j]) - mean;
+    double run = block_exclusive_scan(part, lds_d, total);
+    for (int j = lo; j < hi; ++j) {
+      if (j >= 1) run += (wi[j] - we[j]) - mean;
+      phi[j] = run;
+    }
+  }
+  __syncthreads();
+  double sum_r;
+  {
+    double part = 0.0;
+    for (int j = lo; j < hi; ++j) part += phi[j];
+    block_exclusive_scan(part, lds_d, sum_r);
+  }
+  const double a = dd.periodic ? 0.0 : dd.vhat_amp * sin(dd.phase_per_step * static_cast<double>(step));
+  const double s0 = (0.0 - a + sum_r) / static_cast<double>(N);
+  // s_j and Phi_j = a + sum_{m<j} s_m
+  {
+    double part = 0.0;
+    for (int j = lo; j < hi; ++j) part += s0 - phi[j];
+    __syncthreads();
+    double run = block_exclusive_scan(part, lds_d, total) + a;
+    for (int j = lo; j < hi; ++j) {
+      const double sj = s0 - phi[j];
+      E[j] = sj;
+      phi[j] = run;
+      run += sj;
+    }
+  }
+  __syncthreads();
+  if (!dd.periodic && threadIdx.x == 0) phi[N] = 0.0;
+  // E from the slopes (E[j] holds s_j for j < N)
+  double* tmp = dd.scratch;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) tmp[j] = E[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+    double e;
+    if (dd.periodic) {
+      const int jm = j == 0 ? N - 1 : j - 1;
+      e = -(tmp[jm] + tmp[j]) / 2.0;
+    } else if (j == 0) {
+      e = -tmp[0] - (wi[0] - we[0]);
+    } else if (j == N) {
+      e = -tmp[N - 1] + (wi[N] - we[N]);
+    } else {
+      e = -(tmp[j - 1] + tmp[j]) / 2.0;
+    }
+    E[j] = e;
+    dd.E32[j] = static_cast<float>(e);
+  }
+  __syncthreads();
+  if (!init_mode && static_cast<long long>(step) >= dd.avg_start) {
+    for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+      dd.acc_w[0][j] += we[j];
+      dd.acc_w[1][j] += wi[j];
+      dd.acc_phi[j] += phi[j];
+    }
+    if (threadIdx.x == 0) *dd.acc_count += 1ull;
+  }
+  if (!init_mode && threadIdx.x == 0 && diag_step(dd, step)) *dd.eedf_samples += 1ull;
+  // per-step far-mover state of both species starts empty
+  for (int sp = 0; sp < 2; ++sp) {
+    const SpeciesDev& s = sim.sp[dd.spec0 + sp];
+    for (int j = threadIdx.x; j < nn; j += blockDim.x) s.far_w[j] = 0.0;
+    for (int c = threadIdx.x; c < N; c += blockDim.x) s.far_cell_cnt[c] = 0u;
+    if (threadIdx.x == 0) *s.far_count = 0u;
+  }
+}
+
+// ====================================================================================
+// k_hist: post-push cell histogram of each tile over its window (sort pre-pass).
+// Particles leaving the window (and the unsorted births tail) go to the far list.
+// ====================================================================================
+template <class P>
+__global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
+  using real = typename Part<P>::real;
+  const SimDev& sim = *simp;
+  const int2 tt = sim.tile_table[blockIdx.x];
+  const SpeciesDev& s = sim.sp[tt.x];
+  const DischargeDev& dd = sim.ds[s.ds];
+  const int p = static_cast<int>(*sim.step & 1ull);
+  const TileRange r = tile_range(s, tt.y, p);
+  __shared__ real Elds[kMaxCellsPerTile + 1];
+  __shared__ uint32_t h[kMaxWindow];
+  const real* E = std::is_same<P, P32>::value ? reinterpret_cast<const real*>(dd.E32)
+                                               : reinterpret_cast<const real*>(dd.E64);
+  load_field_window<real>(s, E, r, Elds);
+  for (int k = threadIdx.x; k < s.W; k += blockDim.x) h[k] = 0u;
+  __syncthreads();
+  void* const* in = s.fld[p];
+  for (uint32_t i = r.lo + threadIdx.x; i < r.hi; i += blockDim.x) {
+    Part<P> q;
+    q.load(in, i);
+    int d;
+    real pos, vxn;
+    const int st = push_particle<P>(s, dd, Elds, r, q, d, pos, vxn);
+    if (st != 0) continue;
+    const int k = r.tail ? -1 : window_slot(s, tt.y, d);
+    if (k >= 0) {
+      atomicAdd(&h[k], 1u);
+    } else {
+      const uint32_t e = atomicAdd(s.far_count, 1u);
+      if (e < s.far_cap) {
+        s.far_list[e] = make_uint4(static_cast<uint32_t>(d), i, static_cast<uint32_t>(tt.y), 0u);
+        atomicAdd(&s.far_cell_cnt[d], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  if (!r.tail)
+    for (int k = threadIdx.x; k < s.W; k += blockDim.x)
+      s.hist[static_cast<size_t>(tt.y) * s.W + k] = h[k];
+}
+
+// ====================================================================================
+// k_scan: one workgroup per (discharge, species).  Output order = stable sort of the
+// survivors by cell (ties in input order).  For cell c:
+//   count(c) = sum of the covering tiles' histogram entries + far movers into c,
+//   base(c)  = exclusive scan of count;
+//   a tile t's particles in c start at base(c) + (far movers into c from tiles < t)
+//              + (histogram entries of the covering tiles < t);
+//   a far mover from tile u starts at base(c) + (its rank by index among the far movers
+//              into c) + (histogram entries of the covering tiles < u).
+// ====================================================================================
+constexpr uint32_t kMaxFarGroup = 8192;
+
+__global__ __launch_bounds__(kSolveWG) void k_scan(const SimDev* __restrict__ simp) {
+  const SimDev& sim = *simp;
+  const SpeciesDev& s = sim.sp[blockIdx.x];
+  __shared__ uint32_t lds[kSolveWG / 64 + 1];
+  const int q = static_cast<int>((*sim.step + 1ull) & 1ull);
+  const int N = s.n_cells, W = s.W;
+  const uint32_t fc = *s.far_count;
+  const uint32_t F = fc < s.far_cap ? fc : s.far_cap;
+  if (threadIdx.x == 0 && fc > s.far_cap) atomicOr(sim.error, kErrFarOverflow);
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    s.far_fill[c] = 0u;
+    s.far_base[c] = s.far_cell_cnt[c];
+  }
+  __syncthreads();
+  array_exclusive_scan(s.far_base, N, lds);
+  for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
+    const uint4 v = s.far_list[e];
+    const uint32_t pos = s.far_base[v.x] + atomicAdd(&s.far_fill[v.x], 1u);
+    s.far_grouped[pos] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    const uint32_t g = s.far_cell_cnt[c];
+    const uint32_t gb = s.far_base[c];
+    if (g > kMaxFarGroup) atomicOr(sim.error, kErrFarGroup);
+    const uint32_t gl = g > kMaxFarGroup ? 0u : g;
+    uint32_t run = 0;
+    for_covering(s, c, W, [&](int t, int k) {
+      uint32_t fb = 0;
+      for (uint32_t m = 0; m < gl; ++m) fb += s.far_grouped[gb + m].z < static_cast<uint32_t>(t);
+      const size_t o = static_cast<size_t>(t) * W + k;
+      s.tilerel[o] = run + fb;
+      run += s.hist[o];
+    });
+    s.base[c] = run + g;
+  }
+  __syncthreads();
+  const uint32_t n_surv = array_exclusive_scan(s.base, N, lds);
+  for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
+    const uint4 v = s.far_grouped[e];
+    const int c = static_cast<int>(v.x);
+    const uint32_t g = s.far_cell_cnt[c];
+    const uint32_t gb = s.far_base[c];
+    if (g > kMaxFarGroup) continue;
+    uint32_t rank = 0;
+    for (uint32_t m = 0; m < g; ++m) rank += s.far_grouped[gb + m].y < v.y;
+    uint32_t nb = 0;
+    for_covering(s, c, W, [&](int t, int k) {
+      if (static_cast<uint32_t>(t) < v.z) nb += s.hist[static_cast<size_t>(t) * W + k];
+    });
+    s.far_dest[v.y] = s.base[c] + rank + nb;
+  }
+  uint32_t* cs = s.cell_start + q * (N + 1);
+  for (int c = threadIdx.x; c < N; c += blockDim.x) cs[c] = s.base[c];
+  if (threadIdx.x == 0) {
+    cs[N] = n_surv;
+    s.n_sorted[q] = n_surv;
+  }
+}
+
+// ====================================================================================
+// k_main: the fused particle pass of one tile.
+// ====================================================================================
+template <class P>
+struct MainShared {
+  using real = typename Part<P>::real;
+  real Elds[kMaxCellsPerTile + 1];
+  real dep[kMaxWindow + 1];
+  uint32_t off[kMaxWindow];
+  uint32_t wcnt[kWaves][kMaxWindow];
+  real sv[3][kWG];     // velocities after the push (updated by collisions)
+  real spos[kWG];      // new offset (FP32) or x (FP64)
+  int sd[kWG];         // destination cell
+  uint32_t sid[kWG];
+  uint32_t sw1[kWG], sw2[kWG];
+  int sborn[kWG];
+  real sbv[6][kWG];    // secondary electron and new ion velocities
+  int queue[kWG];
+  int qn;
+  uint32_t wb[kWaves + 1];
+  uint32_t eedf[kMaxEedfBins + 1];
+  uint32_t abs_cnt[2];
+  uint32_t coll[3];
+  double abs_e[2];
+};
+
+// One collision test of a candidate (Sec. 3.8): returns the channel (0 null).
+template <class P>
+__device__ int collide(const SpeciesDev& s, uint32_t id, uint32_t step, uint32_t w1,
+                       uint32_t w2, typename Part<P>::real v[3], typename Part<P>::real vs[3],
+                       typename Part<P>::real vi[3]) {
+  using real = typename Part<P>::real;
+  const double r = u53(w1, w2) * s.nu0;
+  if (s.sp == 0) {
+    const double vx = v[0], vy = v[1], vz = v[2];
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    const double eps = s.energy_c * v2;
+    const double speed = sqrt(v2) * s.vunit;
+    double el, ex, iz;
+    xsec_electron(s.xsec, eps, s.sigma_const, el, ex, iz);
+    const double nu_el = s.n_gas * el * speed;
+    const double nu_ex = s.n_gas * ex * speed;
+    const double nu_iz = s.n_gas * iz * speed;
+    int ch = 0;
+    if (r < nu_el) ch = 1;
+    else if (r < nu_el + nu_ex) ch = 2;
+    else if (r < nu_el + nu_ex + nu_iz) ch = 3;
+    if (ch == 0) return 0;
+    const uint4 b1 = philox(id, step, 1u, 0u, s.key0, s.key1);
+    if (ch == 1) {
+      if constexpr (std::is_same<P, P32>::value) {
+        float n0, n1, n2;
+        direction32(b1, n0, n1, n2);
+        const float vm = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const float cchi = (v[0] * n0 + v[1] * n1 + v[2] * n2) / vm;
+        const float fac = 1.0f - 2.0f * static_cast<float>(s.mass_ratio) * (1.0f - cchi);
+        const float vn = vm * sqrtf(fac);
+        v[0] = vn * n0;
+        v[1] = vn * n1;
+        v[2] = vn * n2;
+      } else {
+        double n0, n1, n2;
+        direction64(b1, n0, n1, n2);
+        const double vm = sqrt(v2);
+        const double cchi = (vx * n0 + vy * n1 + vz * n2) / vm;
+        const double ep = eps * (1.0 - 2.0 * s.mass_ratio * (1.0 - cchi));
+        const double vn = sqrt(ep / s.energy_c);
+        v[0] = vn * n0;
+        v[1] = vn * n1;
+        v[2] = vn * n2;
+      }
+    } else if (ch == 2) {
+      double n0, n1, n2;
+      direction64(b1, n0, n1, n2);
+      const double vn = sqrt((eps - kExcEv) / s.energy_c);
+      v[0] = static_cast<real>(vn * n0);
+      v[1] = static_cast<real>(vn * n1);
+      v[2] = static_cast<real>(vn * n2);
+    } else {
+      const uint4 b2 = philox(id, step, 2u, 0u, s.key0, s.key1);
+      const uint4 b3 = philox(id, step, 3u, 0u, s.key0, s.key1);
+      const uint4 b4 = philox(id, step, 4u, 0u, s.key0, s.key1);
+      const uint4 b5 = philox(id, step, 5u, 0u, s.key0, s.key1);
+      const double er = eps - kIonEv;
+      const double es = u53(b2.x, b2.y) * er;
+      const double epr = er - es;
+      double n0, n1, n2;
+      direction64(b1, n0, n1, n2);
+      const double vp = sqrt(epr / s.energy_c);
+      v[0] = static_cast<real>(vp * n0);
+      v[1] = static_cast<real>(vp * n1);
+      v[2] = static_cast<real>(vp * n2);
+      direction64(b3, n0, n1, n2);
+      const double vsm = sqrt(es / s.energy_c);
+      vs[0] = static_cast<real>(vsm * n0);
+      vs[1] = static_cast<real>(vsm * n1);
+      vs[2] = static_cast<real>(vsm * n2);
+      double z0, z1, z2, z3;
+      normals64(b4, z0, z1);
+      normals64(b5, z2, z3);
+      vi[0] = static_cast<real>(s.vth_gas * z0);
+      vi[1] = static_cast<real>(s.vth_gas * z1);
+      vi[2] = static_cast<real>(s.vth_gas * z2);
+    }
+    return ch;
+  }
+  // ion: sample the gas atom, test with the relative speed
+  const uint4 b1 = philox(id, step, 1u, 0u, s.key0, s.key1);
+  const uint4 b2 = philox(id, step, 2u, 0u, s.key0, s.key1);
+  double z0, z1, z2, z3;
+  normals64(b1, z0, z1);
+  normals64(b2, z2, z3);
+  const double vg[3] = {s.vth_gas * z0, s.vth_gas * z1, s.vth_gas * z2};
+  const double vv[3] = {v[0], v[1], v[2]};
+  const double g[3] = {vv[0] - vg[0], vv[1] - vg[1], vv[2] - vg[2]};
+  const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  const double eps = s.energy_c * g2;
+  const double speed = sqrt(g2) * s.vunit;
+  double sis, scx;
+  xsec_ion(s.xsec, eps, sis, scx);
+  const double nu_is = s.n_gas * sis * speed;
+  const double nu_cx = s.n_gas * scx * speed;
+  int ch = 0;
+  if (r < nu_is) ch = 1;
+  else if (r < nu_is + nu_cx) ch = 2;
+  if (ch == 1) {
+    const uint4 b3 = philox(id, step, 3u, 0u, s.key0, s.key1);
+    double n0, n1, n2;
+    direction64(b3, n0, n1, n2);
+    const double gm = sqrt(g2);
+    const double nn[3] = {n0, n1, n2};
+    for (int a = 0; a < 3; ++a) v[a] = static_cast<real>(0.5 * (vv[a] + vg[a]) + 0.5 * gm * nn[a]);
+  } else if (ch == 2) {
+    for (int a = 0; a < 3; ++a) v[a] = static_cast<real>(vg[a]);
+  }
+  return ch;
+}
+
+template <class P>
+__device__ __forceinline__ void far_deposit(const SpeciesDev& s, int d,
+                                            typename Part<P>::real pos) {
+  double f;
+  if constexpr (std::is_same<P, P32>::value) {
+    f = static_cast<double>(pos);
+  } else {
+    f = pos - floor(pos);
+  }
+  int dn = d + 1;
+  if (s.periodic && dn == s.n_cells) dn = 0;
+  atomicAdd(&s.far_w[d], 1.0 - f);
+  atomicAdd(&s.far_w[dn], f);
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
+  using real = typename Part<P>::real;
+  const SimDev& sim = *simp;
+  const int2 tt = sim.tile_table[blockIdx.x];
+  const SpeciesDev& s = sim.sp[tt.x];
+  const DischargeDev& dd = sim.ds[s.ds];
+  const unsigned long long step = *sim.step;
+  const uint32_t step32 = static_cast<uint32_t>(step);
+  const int p = static_cast<int>(step & 1ull), pq = p ^ 1;
+  const TileRange r = tile_range(s, tt.y, p);
+  const int tile = tt.y;
+  __shared__ MainShared<P> sh;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const bool eedf_on = s.sp == 0 && diag_step(dd, step);
+  const bool far_ok = (*sim.error & kErrFarOverflow) == 0u;
+  const uint32_t n_out = s.n_sorted[pq];
+  const real* E = std::is_same<P, P32>::value ? reinterpret_cast<const real*>(dd.E32)
+                                               : reinterpret_cast<const real*>(dd.E64);
+  load_field_window<real>(s, E, r, sh.Elds);
+  const int W = s.W;
+  for (int k = tid; k < W; k += kWG) {
+    int c = tile * s.C - s.D + k;
+    if (s.periodic) {
+      c %= s.n_cells;
+      if (c < 0) c += s.n_cells;
+    }
+    sh.off[k] = (!r.tail && c >= 0 && c < s.n_cells)
+                    ? s.base[c] + s.tilerel[static_cast<size_t>(tile) * W + k]
+                    : 0u;
+  }
+  for (int k = tid; k <= W; k += kWG) sh.dep[k] = real(0);
+  if (eedf_on)
+    for (int k = tid; k <= dd.eedf_bins; k += kWG) sh.eedf[k] = 0u;
+  if (tid == 0) {
+    sh.qn = 0;
+    sh.wb[kWaves] = 0u;
+    sh.abs_cnt[0] = sh.abs_cnt[1] = 0u;
+    sh.coll[0] = sh.coll[1] = sh.coll[2] = 0u;
+    sh.abs_e[0] = sh.abs_e[1] = 0.0;
+  }
+  int nbits = 0;
+  while ((1 << nbits) < W) ++nbits;
+  __syncthreads();
+  void* const* in = s.fld[p];
+  void* const* out = s.fld[pq];
+  const SpeciesDev* ion = s.sp == 0 ? &sim.sp[tt.x + 1] : nullptr;
+  for (uint32_t base_i = r.lo; base_i < r.hi; base_i += kWG) {
+    const uint32_t i = base_i + tid;
+    const bool valid = i < r.hi;
+    for (int k = tid; k < kWaves * W; k += kWG) sh.wcnt[k / W][k % W] = 0u;
+    Part<P> q;
+    int st = 4, d = 0;
+    real pos = real(0), vxn = real(0);
+    if (valid) {
+      q.load(in, i);
+      st = push_particle<P>(s, dd, sh.Elds, r, q, d, pos, vxn);
+      const double v2 = static_cast<double>(vxn) * static_cast<double>(vxn) +
+                        static_cast<double>(q.vy) * static_cast<double>(q.vy) +
+                        static_cast<double>(q.vz) * static_cast<double>(q.vz);
+      if (eedf_on && st != 3) {
+        const double eps = s.energy_c * v2;
+        const double b = floor(eps * dd.eedf_inv_width);
+        const int bin = b >= static_cast<double>(dd.eedf_bins) ? dd.eedf_bins : static_cast<int>(b);
+        atomicAdd(&sh.eedf[bin], 1u);
+      }
+      if (st == 1 || st == 2) {
+        atomicAdd(&sh.abs_cnt[st - 1], 1u);
+        atomicAdd(&sh.abs_e[st - 1], s.energy_c * v2);
+      } else if (st == 3) {
+        atomicOr(sim.error, kErrState);
+      } else {
+        sh.sv[0][tid] = vxn;
+        sh.sv[1][tid] = q.vy;
+        sh.sv[2][tid] = q.vz;
+        sh.sborn[tid] = 0;
+        if (s.t0 != 0u) {
+          const uint4 b0 = philox(q.id, step32, 0u, 0u, s.key0, s.key1);
+          if (b0.x < s.t0) {
+            sh.sid[tid] = q.id;
+            sh.sw1[tid] = b0.y;
+            sh.sw2[tid] = b0.z;
+            sh.sd[tid] = d;
+            sh.spos[tid] = pos;
+            const int slot = atomicAdd(&sh.qn, 1);
+            sh.queue[slot] = tid;
+          }
+        }
+      }
+    }
+    __syncthreads();  // B1: candidate queue complete
+    const int qn = sh.qn;
+    for (int qi = tid; qi < qn; qi += kWG) {
+      const int L = sh.queue[qi];
+      real v[3] = {sh.sv[0][L], sh.sv[1][L], sh.sv[2][L]};
+      real vs[3], vi[3];
+      const int ch = collide<P>(s, sh.sid[L], step32, sh.sw1[L], sh.sw2[L], v, vs, vi);
+      if (ch > 0) {
+        atomicAdd(&sh.coll[ch - 1], 1u);
+        sh.sv[0][L] = v[0];
+        sh.sv[1][L] = v[1];
+        sh.sv[2][L] = v[2];
+        if (s.sp == 0 && ch == 3) {
+          sh.sborn[L] = 1;
+          for (int a = 0; a < 3; ++a) {
+            sh.sbv[a][L] = vs[a];
+            sh.sbv[3 + a][L] = vi[a];
+          }
+        }
+      }
+    }
+    __syncthreads();  // B2: collisions done
+    real vy = q.vy, vz = q.vz;
+    bool born = false;
+    if (st == 0) {
+      vxn = sh.sv[0][tid];
+      vy = sh.sv[1][tid];
+      vz = sh.sv[2][tid];
+      born = sh.sborn[tid] != 0;
+    }
+    const int k = (st == 0 && !r.tail) ? window_slot(s, tile, d) : -1;
+    const bool near = k >= 0;
+    unsigned long long m = __ballot(near);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = near && ((k >> b) & 1);
+      const unsigned long long mb = __ballot(bit);
+      m &= (near && ((k >> b) & 1)) ? mb : ~mb;
+    }
+    const int rank = __popcll(m & lt);
+    if (near && rank == 0) sh.wcnt[wv][k] = static_cast<uint32_t>(__popcll(m));
+    const unsigned long long bm = __ballot(born);
+    const int brank_w = __popcll(bm & lt);
+    if (lane == 0) sh.wb[wv] = static_cast<uint32_t>(__popcll(bm));
+    __syncthreads();  // B3: per-wave counts
+    for (int kk = tid; kk < W; kk += kWG) {
+      uint32_t run = sh.off[kk];
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = sh.wcnt[w][kk];
+        sh.wcnt[w][kk] = run;
+        run += c;
+      }
+      sh.off[kk] = run;
+    }
+    if (tid == kWG - 1) {
+      uint32_t run = sh.wb[kWaves];
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = sh.wb[w];
+        sh.wb[w] = run;
+        run += c;
+      }
+      sh.wb[kWaves] = run;
+    }
+    __syncthreads();  // B4: offsets known
+    if (st == 0) {
+      uint32_t dst;
+      bool ok;
+      if (near) {
+        dst = sh.wcnt[wv][k] + static_cast<uint32_t>(rank);
+        ok = true;
+      } else {
+        dst = far_ok ? s.far_dest[i] : 0u;
+        ok = far_ok;
+      }
+      if (ok && dst >= n_out) {
+        atomicOr(sim.error, kErrState);
+        ok = false;
+      }
+      if (ok) store_record<P>(out, dst, d, pos, vxn, vy, vz, q.id);
+      if (near) {
+        if constexpr (std::is_same<P, P32>::value) {
+          atomicAdd(&sh.dep[k], 1.0f - pos);
+          atomicAdd(&sh.dep[k + 1], pos);
+        } else {
+          const double f = pos - floor(pos);
+          atomicAdd(&sh.dep[k], 1.0 - f);
+          atomicAdd(&sh.dep[k + 1], f);
+        }
+      } else if (ok) {
+        far_deposit<P>(s, d, pos);
+      }
+      if (born) {
+        const uint32_t brank = sh.wb[wv] + static_cast<uint32_t>(brank_w);
+        const uint32_t si = r.lo + brank;
+        store_record<P>(s.stage[0], si, d, pos, sh.sbv[0][tid], sh.sbv[1][tid], sh.sbv[2][tid], 0u);
+        store_record<P>(s.stage[1], si, d, pos, sh.sbv[3][tid], sh.sbv[4][tid], sh.sbv[5][tid], 0u);
+        if (near) {
+          if constexpr (std::is_same<P, P32>::value) {
+            atomicAdd(&sh.dep[k], 1.0f - pos);
+            atomicAdd(&sh.dep[k + 1], pos);
+          } else {
+            const double f = pos - floor(pos);
+            atomicAdd(&sh.dep[k], 1.0 - f);
+            atomicAdd(&sh.dep[k + 1], f);
+          }
+        } else {
+          far_deposit<P>(s, d, pos);
+        }
+        far_deposit<P>(*ion, d, pos);
+      }
+    }
+    if (tid == 0) sh.qn = 0;
+    __syncthreads();  // B5: LDS free for the next chunk
+  }
+  // tile epilogue
+  if (!r.tail) {
+    real* part = static_cast<real*>(s.partial) + static_cast<size_t>(tile) * (W + 1);
+    for (int k = tid; k <= W; k += kWG) part[k] = sh.dep[k];
+  }
+  if (tid == 0) {
+    s.birth_cnt[tile] = sh.wb[kWaves];
+    s.tile_first[tile] = r.lo;
+    if (sh.abs_cnt[0]) atomicAdd(&s.absorbed[0], static_cast<unsigned long long>(sh.abs_cnt[0]));
+    if (sh.abs_cnt[1]) atomicAdd(&s.absorbed[1], static_cast<unsigned long long>(sh.abs_cnt[1]));
+    if (sh.abs_cnt[0]) atomicAdd(&s.absorbed_energy[0], sh.abs_e[0]);
+    if (sh.abs_cnt[1]) atomicAdd(&s.absorbed_energy[1], sh.abs_e[1]);
+    for (int c = 0; c < 3; ++c)
+      if (sh.coll[c]) atomicAdd(&s.collisions[c], static_cast<unsigned long long>(sh.coll[c]));
+  }
+  if (eedf_on)
+    for (int k = tid; k <= dd.eedf_bins; k += kWG)
+      if (sh.eedf[k]) atomicAdd(&dd.eedf[k], static_cast<unsigned long long>(sh.eedf[k]));
+}
+
+// ====================================================================================
+// k_finalize: one workgroup per (discharge, species).  Births are appended after the
+// sorted survivors in the order of their parents' input index (the electron tiles are
+// in index order and each keeps its births in index order); the children take the next
+// ids of their species.  The last workgroup to finish advances the step counter.
+// ====================================================================================
+template <class P>
+__global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict__ simp) {
+  using real = typename Part<P>::real;
+  const SimDev& sim = *simp;
+  const SpeciesDev& s = sim.sp[blockIdx.x];
+  const SpeciesDev& se = sim.sp[blockIdx.x - s.sp];
+  __shared__ uint32_t lds[kSolveWG / 64 + 1];
+  __shared__ uint32_t sh_fit, sh_nid;
+  const unsigned long long step = *sim.step;
+  const int q = static_cast<int>((step + 1ull) & 1ull);
+  const int nt = se.n_tiles + se.n_tail;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) s.birth_base[t] = se.birth_cnt[t];
+  __syncthreads();
+  const uint32_t B = array_exclusive_scan(s.birth_base, nt, lds);
+  const uint32_t n_surv = s.n_sorted[q];
+  if (threadIdx.x == 0) {
+    s.birth_base[nt] = B;
+    uint32_t fit = B;
+    const uint32_t room = s.cap > n_surv ? s.cap - n_surv : 0u;
+    if (fit > room) {
+      fit = room;
+      atomicOr(sim.error, kErrCapacity);
+    }
+    const uint32_t nid = *s.next_id;
+    if (static_cast<unsigned long long>(nid) + fit > 0xFFFFFFFFull) {
+      fit = 0xFFFFFFFFu - nid;
+      atomicOr(sim.error, kErrIdOverflow);
+    }
+    sh_fit = fit;
+    sh_nid = nid;
+  }
+  __syncthreads();
+  const uint32_t fit = sh_fit, nid = sh_nid;
+  void* const* src = se.stage[s.sp];
+  void* const* dst = s.fld[q];
+  for (uint32_t b = threadIdx.x; b < fit; b += blockDim.x) {
+    int lo = 0, hi = nt;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s.birth_base[mid] <= b) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t si = se.tile_first[lo] + (b - s.birth_base[lo]);
+    const uint32_t di = n_surv + b;
+    int cell = 0;
+    real pos;
+    if constexpr (std::is_same<P, P32>::value) {
+      cell = static_cast<const int*>(src[F32_CELL])[si];
+      pos = static_cast<const float*>(src[F32_OFF])[si];
+    } else {
+      pos = static_cast<const double*>(src[F64_X])[si];
+    }
+    store_record<P>(dst, di, cell, pos, static_cast<const real*>(src[F_VX])[si],
+                    static_cast<const real*>(src[F_VY])[si],
+                    static_cast<const real*>(src[F_VZ])[si], nid + b);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *s.psteps += static_cast<unsigned long long>(s.n_total[q ^ 1]);
+    s.n_total[q] = n_surv + fit;
+    *s.next_id = nid + fit;
+    *s.births += fit;
+    __threadfence();
+    const uint32_t done = atomicAdd(sim.fin_count, 1u);
+    if (done == static_cast<uint32_t>(sim.n_spec) - 1u) {
+      *sim.fin_count = 0u;
+      __threadfence();
+      *sim.step = step + 1ull;
+    }
+  }
+}
+
+// ====================================================================================
+// host launchers
+// ====================================================================================
+void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
+  dim3 grid((li.max_nodes + 255) / 256, li.n_spec);
+  if (li.fp32) k_combine<float><<<grid, 256, 0, st>>>(sim);
+  else k_combine<double><<<grid, 256, 0, st>>>(sim);
+}
+
+void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st) {
+  k_solve<<<li.n_ds, kSolveWG, 0, st>>>(sim, init_mode);
+}
+
+void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
+  if (li.fp32) k_hist<P32><<<li.total_tiles, kWG, 0, st>>>(sim);
+  else k_hist<P64><<<li.total_tiles, kWG, 0, st>>>(sim);
+}
+
+void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
+  k_scan<<<li.n_spec, kSolveWG, 0, st>>>(sim);
+}
+
+void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
+  if (li.fp32) k_main<P32><<<li.total_tiles, kWG, 0, st>>>(sim);
+  else k_main<P64><<<li.total_tiles, kWG, 0, st>>>(sim);
+}
+
+void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
+  if (li.fp32) k_finalize<P32><<<li.n_spec, kSolveWG, 0, st>>>(sim);
+  else k_finalize<P64><<<li.n_spec, kSolveWG, 0, st>>>(sim);
+}
+
+}  // namespace fspic

@@ -1,0 +1,173 @@
+// physics_host.cpp -- host-side derivation of the normalised constants of one discharge
+// (Sec. 3.3) and of the tile geometry of the step kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host_common.h"
+
+namespace fspic {
+
+namespace {
+constexpr double kQe = 1.602176634e-19;    // CODATA 2018
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKb = 1.380649e-23;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kTwoPiH = 6.283185307179586476925286766559;
+
+// Synthetic Ar-like cross sections (m^2) in place of the paper's unprinted argon fits.
+void cross_sections(int model, int species, double eps, double sc, double s[3]) {
+  s[0] = s[1] = s[2] = 0.0;
+  if (model == PIC_XS_CONST_E_ELASTIC) {
+    if (species == 0) s[0] = sc;
+    return;
+  }
+  if (model != PIC_XS_AR_LIKE) return;
+  if (species == 0) {
+    const double xe = eps / 12.0;
+    s[0] = 3e-19 * (xe + 0.05) / (1.0 + xe * xe);
+    if (eps > 11.5) {
+      const double u = (eps - 11.5) / 20.0;
+      s[1] = 2e-20 * (2.0 * u) / (1.0 + u * u);
+    }
+    if (eps > 15.8) {
+      const double u = (eps - 15.8) / 60.0;
+      s[2] = 3e-20 * (2.0 * u) / (1.0 + u * u);
+    }
+  } else {
+    s[0] = 2e-19 * (1.0 + 2.0 / (1.0 + eps)) / (1.0 + eps / 100.0);
+    s[1] = 3e-19 * (1.0 + 1.0 / (1.0 + eps)) / (1.0 + eps / 1000.0);
+  }
+}
+
+// Null-collision frequency, computed once per species (Sec. 3.8): the largest total
+// frequency n_g sum sigma v over 0..5000 eV (0.01 eV grid) raised by 1e-9; for a
+// constant sigma, the frequency at eps_cap.
+double null_frequency(const pic_config& c, int species, double n_gas, double mass) {
+  if (n_gas <= 0.0 || c.xsec_model == PIC_XS_NONE) return 0.0;
+  if (c.xsec_model == PIC_XS_CONST_E_ELASTIC) {
+    if (species != 0) return 0.0;
+    return n_gas * c.sigma_const_m2 * std::sqrt(2.0 * kQe * c.eps_cap_ev / mass);
+  }
+  double best = 0.0;
+  for (int k = 0; k <= 500000; ++k) {
+    const double eps = static_cast<double>(k) * 0.01;
+    double s[3];
+    cross_sections(static_cast<int>(c.xsec_model), species, eps, c.sigma_const_m2, s);
+    const double nu = n_gas * (s[0] + s[1] + s[2]) * std::sqrt(2.0 * kQe * eps / mass);
+    best = nu > best ? nu : best;
+  }
+  return best * (1.0 + 1e-9);
+}
+
+int largest_divisor_at_most(int n, int c) {
+  for (int d = std::min(c, n); d >= 1; --d)
+    if (n % d == 0) return d;
+  return 1;
+}
+}  // namespace
+
+double electron_mass() { return kMe; }
+double ion_mass(const pic_config& c) { return c.mass_i_amu * kAmu; }
+
+int validate_config(const pic_config& c, std::string* why) {
+  auto bad = [&](const char* m) {
+    *why = m;
+    return PIC_ERR_ARG;
+  };
+  if (c.abi_version != FSPIC_ABI_VERSION) return bad("abi_version mismatch");
+  if (c.precision != PIC_FP64 && c.precision != PIC_FP32_OFFSET) return bad("precision");
+  if (c.n_cells < 1 || c.n_cells > kMaxCells) return bad("n_cells out of [1, 16384]");
+  if (c.periodic && c.n_cells < 3) return bad("periodic box needs >= 3 cells");
+  if (c.n_e0 < 1) return bad("n_e0 must be >= 1 (it sets the macro-particle weight)");
+  if (c.capacity_e < c.n_e0 || c.capacity_i < c.n_i0) return bad("capacity below n0");
+  if (c.capacity_e >= 0x7FFFFFFFull || c.capacity_i >= 0x7FFFFFFFull)
+    return bad("capacity must be < 2^31 - 1");
+  if (!(c.length_m > 0) || !(c.dt_s > 0) || !(c.n0_m3 > 0) || !(c.mass_i_amu > 0))
+    return bad("length, dt, n0 and ion mass must be positive");
+  if (!(c.te_ev >= 0) || !(c.ti_ev >= 0) || !(c.gas_pa >= 0) || !(c.gas_k > 0))
+    return bad("temperatures / gas pressure");
+  if (c.xsec_model > PIC_XS_AR_LIKE) return bad("xsec_model");
+  if (c.load_kind > PIC_LOAD_QUIET_LANGMUIR) return bad("load_kind");
+  if (c.eedf_bins > 256) return bad("eedf_bins > 256");
+  if (c.eedf_bins > 0 && !(c.eedf_max_ev > 0)) return bad("eedf_max_ev");
+  if (c.xsec_model == PIC_XS_CONST_E_ELASTIC && !(c.eps_cap_ev > 0)) return bad("eps_cap_ev");
+  return PIC_OK;
+}
+
+int derive(const pic_config& c, pic_derived* k) {
+  std::memset(k, 0, sizeof(*k));
+  k->dx = c.length_m / static_cast<double>(c.n_cells);
+  k->weight_per_area = c.n0_m3 * c.length_m / static_cast<double>(c.n_e0);
+  const double mass[2] = {kMe, c.mass_i_amu * kAmu};
+  for (int s = 0; s < 2; ++s) {
+    const double q = s == 0 ? -1.0 : 1.0;
+    // eq. push_velocity with Q = e W, M = m W
+    k->kappa[s] = q * kQe * kQe * k->weight_per_area * c.dt_s * c.dt_s /
+                  (kEps0 * mass[s] * k->dx);
+  }
+  k->phi_scale = kQe * k->weight_per_area * k->dx / kEps0;
+  k->vunit = k->dx / c.dt_s;
+  for (int s = 0; s < 2; ++s) {
+    k->energy_c[s] = 0.5 * mass[s] * k->vunit * k->vunit / kQe;
+    const double t_ev = s == 0 ? c.te_ev : c.ti_ev;
+    k->vth[s] = std::sqrt(t_ev * kQe / mass[s]) / k->vunit;
+  }
+  k->vth_gas = std::sqrt(kKb * c.gas_k / mass[1]) / k->vunit;
+  k->n_gas = c.gas_pa > 0.0 ? c.gas_pa / (kKb * c.gas_k) : 0.0;
+  for (int s = 0; s < 2; ++s) {
+    k->nu0[s] = null_frequency(c, s, k->n_gas, mass[s]);
+    k->p0[s] = 1.0 - std::exp(-c.dt_s * k->nu0[s]);  // eq. null_collision
+    const double t = std::floor(k->p0[s] * 4294967296.0);
+    k->t0[s] = t >= 4294967295.0 ? 4294967295u : static_cast<uint32_t>(t);
+  }
+  k->vhat_amp = c.v0_volt / k->phi_scale;
+  k->drive_phase_per_step = kTwoPiH * c.freq_hz * c.dt_s;
+  TileChoice tc[2];
+  choose_tiles(c, tc);
+  for (int s = 0; s < 2; ++s) {
+    k->cells_per_tile[s] = static_cast<uint32_t>(tc[s].C);
+    k->window[s] = static_cast<uint32_t>(tc[s].D);
+  }
+  return PIC_OK;
+}
+
+// Tile geometry.  A workgroup owns C consecutive cells (the paper's "one thread block
+// per sorting cell", Sec. 3.2, with C cells per block instead of one) and sorts the
+// particles that stay within D cells of them; the rest take the far-mover path.
+void choose_tiles(const pic_config& c, TileChoice tc[2]) {
+  const int N = static_cast<int>(c.n_cells);
+  const uint64_t n0[2] = {c.n_e0, c.n_i0};
+  const int d_default[2] = {32, 4};
+  for (int s = 0; s < 2; ++s) {
+    int C;
+    if (c.cells_per_tile[s] > 0) {
+      C = static_cast<int>(c.cells_per_tile[s]);
+    } else {
+      const double ppc = std::max(1.0, static_cast<double>(n0[s]) / N);
+      C = static_cast<int>(std::lround(4096.0 / ppc));
+    }
+    C = std::max(1, std::min(C, std::min(64, N)));
+    int D = c.window[s] > 0 ? static_cast<int>(c.window[s]) : d_default[s];
+    if (c.periodic) {
+      for (;;) {
+        C = largest_divisor_at_most(N, C);
+        const int dmax = (N - 2 * C - 1) / 2;
+        if (dmax >= 0 || C == 1) {
+          D = std::max(0, std::min(D, dmax));
+          break;
+        }
+        C = C - 1;
+      }
+    }
+    D = std::max(0, std::min(D, (kMaxWindow - C) / 2));
+    tc[s].C = C;
+    tc[s].D = D;
+    tc[s].W = C + 2 * D;
+    tc[s].n_tiles = (N + C - 1) / C;
+    tc[s].n_tail = c.tail_groups > 0 ? static_cast<int>(c.tail_groups) : 4;
+  }
+}
+
+}  // namespace fspic

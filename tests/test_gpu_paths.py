@@ -1,0 +1,182 @@
+"""GPU parity of the less common paths of the step through the C ABI: far movers (more
+than `window` cells in one step), an unsorted births tail handed in by the caller, the
+general device sort, batched discharges, HIP-graph replay, and one step at the full size
+of the large single discharge.  Same bar as test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+import workloads
+from test_gpu_parity import compare, tallies_of, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fspic():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1104_3998_amd as m
+    m.lib()
+    return m
+
+
+def one_step_vs_oracle(fspic, oracle_mod, wl, precision, edit=None, sort_all=False):
+    fp32 = precision == "fp32_offset"
+    sim = fspic.Simulation(wl, precision)
+    st = sim.get_state()
+    if edit is not None:
+        edit(st)
+        sim.set_state(st, sort_all=sort_all)
+        st = sim.get_state()
+    base = tallies_of(sim.diagnostics())
+    orc = oracle_mod.Oracle(wl, fp32_offset=fp32)
+    to_oracle(orc, st, fp32)
+    sim.step(1)
+    orc.step(1)
+    out = compare(sim, orc, fp32, "one step", base)
+    sim.close()
+    return st, out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+def test_far_movers(fspic, oracle_mod, precision):
+    """Electrons sent 40-90 cells in one step (window 31 cells) take the far-mover path and
+    must land at the same place in the stable order."""
+    wl = workloads.periodic_c1(xsec="none", gas_pa=0.0)
+    print("far movers", precision, flush=True)
+
+    def edit(st):
+        rng = np.random.default_rng(7)
+        idx = rng.choice(st[0]["n"], 300, replace=False)
+        key = "vxf" if precision == "fp32_offset" else "vx"
+        st[0][key][idx] = rng.uniform(40, 90, 300) * rng.choice([-1, 1], 300)
+
+    one_step_vs_oracle(fspic, oracle_mod, wl, precision, edit)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+@pytest.mark.parametrize("tail", [137, "all"])
+def test_unsorted_tail(fspic, oracle_mod, precision, tail):
+    """A state whose last particles are not in cell order (as after births): the step sorts
+    them in at their input rank."""
+    wl = dict(workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0))
+    print("tail", tail, precision, flush=True)
+
+    def edit(st):
+        rng = np.random.default_rng(3)
+        for s in (0, 1):
+            a = st[s]
+            n = a["n"]
+            k = n if tail == "all" else tail
+            perm = np.arange(n)
+            moved = rng.choice(n, k, replace=False)
+            keep = np.setdiff1d(perm, moved)
+            order = np.concatenate([keep, rng.permutation(moved)])
+            for name, arr in list(a.items()):
+                if isinstance(arr, np.ndarray) and arr.shape == (n,):
+                    a[name] = arr[order].copy()
+            a["n_sorted"] = n - k
+
+    one_step_vs_oracle(fspic, oracle_mod, wl, precision, edit)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+def test_general_sort_of_shuffled_state(fspic, oracle_mod, precision):
+    """sort_all: the device sorts a shuffled array stably by cell (ties in input order)."""
+    wl = workloads.periodic_c1()
+    fp32 = precision == "fp32_offset"
+    sim = fspic.Simulation(wl, precision)
+    st = sim.get_state()
+    rng = np.random.default_rng(11)
+    shuffled = {}
+    for s in (0, 1):
+        a = st[s]
+        n = a["n"]
+        order = rng.permutation(n)
+        for name, arr in list(a.items()):
+            if isinstance(arr, np.ndarray) and arr.shape == (n,):
+                a[name] = arr[order].copy()
+        cells = a["cell"] if fp32 else np.floor(a["x"]).astype(np.int64)
+        shuffled[s] = a["id"][np.argsort(cells, kind="stable")]
+    sim.set_state(st, sort_all=True)
+    st2 = sim.get_state()
+    for s in (0, 1):
+        assert st2[s]["n_sorted"] == st2[s]["n"]
+        assert np.array_equal(st2[s]["id"], shuffled[s])
+    sim.close()
+
+
+def test_batched_discharges_match_oracle_each(fspic, oracle_mod):
+    """Three discharges of the batched scan (particle counts scaled down) in one launch per
+    kernel: each matches its own oracle run, and discharge 1 equals the same discharge
+    simulated alone."""
+    wls = workloads.batched_c4(n_discharges=3, scale=0.01)
+    print("batched", [(w["n_cells"], w["n_e0"]) for w in wls], flush=True)
+    sim = fspic.Simulation(wls, "fp64")
+    orcs = []
+    for d, wl in enumerate(wls):
+        o = oracle_mod.Oracle(wl)
+        o.load()
+        orcs.append(o)
+    for k in range(5):
+        sim.step(1)
+        for d, o in enumerate(orcs):
+            o.step(1)
+    for d, o in enumerate(orcs):
+        st = sim.get_state(d)
+        for s in (0, 1):
+            assert np.array_equal(st[s]["id"], o.particles(s)["id"]), (d, s)
+            wo = o.grid("w_e" if s == 0 else "w_i")
+            assert np.max(np.abs(st[s]["w"] - wo)) <= 1e-12 * wo.max()
+    alone = fspic.Simulation(wls[1], "fp64")
+    alone.step(5)
+    a = alone.get_state()
+    b = sim.get_state(1)
+    for s in (0, 1):
+        assert np.array_equal(a[s]["id"], b[s]["id"])
+        assert np.max(np.abs(a[s]["x"] - b[s]["x"])) < 1e-12 * wls[1]["n_cells"]
+    alone.close()
+    sim.close()
+
+
+def test_graph_replay_equals_eager(fspic):
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0)
+    a = fspic.Simulation(wl, "fp64")
+    b = fspic.Simulation(wl, "fp64")
+    b.set_graph(10)
+    a.step(30)
+    b.step(30)
+    sa, sb = a.get_state(), b.get_state()
+    assert sa["step"] == sb["step"] == 30
+    for s in (0, 1):
+        assert np.array_equal(sa[s]["id"], sb[s]["id"])
+        assert np.max(np.abs(sa[s]["x"] - sb[s]["x"])) < 1e-9
+        assert np.max(np.abs(sa[s]["w"] - sb[s]["w"])) <= 1e-12 * sa[s]["w"].max()
+    da, db = a.diagnostics(), b.diagnostics()
+    assert list(da.births) == list(db.births)
+    assert [list(r) for r in da.collisions] == [list(r) for r in db.collisions]
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32_offset", "fp64"])
+def test_full_size_large_discharge_one_step(fspic, oracle_mod, precision):
+    """The large single discharge at full size (4096 cells, 1e7 + 1e7), in the launch
+    configuration the benchmark times: a few steps, then one step from the identical state
+    against the oracle over every particle."""
+    wl = workloads.large_c3()
+    fp32 = precision == "fp32_offset"
+    print("full size", precision, flush=True)
+    sim = fspic.Simulation(wl, precision)
+    sim.set_graph(2)
+    sim.step(4)
+    st = sim.get_state()
+    base = tallies_of(sim.diagnostics())
+    orc = oracle_mod.Oracle(wl, fp32_offset=fp32)
+    to_oracle(orc, st, fp32)
+    del st
+    sim.step(1)
+    orc.step(1)
+    compare(sim, orc, fp32, "full size " + precision, base)
+    sim.close()
