@@ -57,8 +57,10 @@ struct Part<P64> {
   }
 };
 
-// position of a particle after the push: cell d and offset (FP32) or absolute x (FP64)
-template <class P>
+// Stores one record: cell d and offset (FP32) or absolute x (FP64), velocity, and the id
+// unless kWithId is false (birth staging keeps no id: k_finalize numbers the births when it
+// appends them, and the staging arrays have no id field).
+template <class P, bool kWithId = true>
 __device__ __forceinline__ void store_record(void* const* f, uint32_t i, int d,
                                              typename Part<P>::real pos,
                                              typename Part<P>::real vx,
@@ -74,7 +76,7 @@ __device__ __forceinline__ void store_record(void* const* f, uint32_t i, int d,
   static_cast<real*>(f[F_VX])[i] = vx;
   static_cast<real*>(f[F_VY])[i] = vy;
   static_cast<real*>(f[F_VZ])[i] = vz;
-  static_cast<uint32_t*>(f[F_ID])[i] = id;
+  if constexpr (kWithId) static_cast<uint32_t*>(f[F_ID])[i] = id;
 }
 
 struct TileRange {
@@ -368,10 +370,14 @@ __global__ __launch_bounds__(kSolveWG) void k_scan(const SimDev* __restrict__ si
   array_exclusive_scan(s.far_base, N, lds);
   for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
     const uint4 v = s.far_list[e];
+    if (v.x >= static_cast<uint32_t>(N)) {
+      atomicOr(sim.error, kErrState);
+      continue;
+    }
     const uint32_t pos = s.far_base[v.x] + atomicAdd(&s.far_fill[v.x], 1u);
-    s.far_grouped[pos] = v;
+    if (pos < F) s.far_grouped[pos] = v;
   }
-  __threadfence_block();
+  __threadfence();
   __syncthreads();
   for (int c = threadIdx.x; c < N; c += blockDim.x) {
     const uint32_t g = s.far_cell_cnt[c];
@@ -392,6 +398,7 @@ __global__ __launch_bounds__(kSolveWG) void k_scan(const SimDev* __restrict__ si
   const uint32_t n_surv = array_exclusive_scan(s.base, N, lds);
   for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
     const uint4 v = s.far_grouped[e];
+    if (v.x >= static_cast<uint32_t>(N) || v.y >= s.cap) continue;
     const int c = static_cast<int>(v.x);
     const uint32_t g = s.far_cell_cnt[c];
     const uint32_t gb = s.far_base[c];
@@ -746,11 +753,13 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       } else if (ok) {
         far_deposit<P>(s, d, pos);
       }
-      if (born) {
+      if (born && r.lo + sh.wb[wv] + static_cast<uint32_t>(brank_w) < s.cap) {
         const uint32_t brank = sh.wb[wv] + static_cast<uint32_t>(brank_w);
         const uint32_t si = r.lo + brank;
-        store_record<P>(s.stage[0], si, d, pos, sh.sbv[0][tid], sh.sbv[1][tid], sh.sbv[2][tid], 0u);
-        store_record<P>(s.stage[1], si, d, pos, sh.sbv[3][tid], sh.sbv[4][tid], sh.sbv[5][tid], 0u);
+        store_record<P, false>(s.stage[0], si, d, pos, sh.sbv[0][tid], sh.sbv[1][tid],
+                               sh.sbv[2][tid], 0u);
+        store_record<P, false>(s.stage[1], si, d, pos, sh.sbv[3][tid], sh.sbv[4][tid],
+                               sh.sbv[5][tid], 0u);
         if (near) {
           if constexpr (std::is_same<P, P32>::value) {
             atomicAdd(&sh.dep[k], 1.0f - pos);
@@ -839,6 +848,7 @@ __global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict_
     }
     const uint32_t si = se.tile_first[lo] + (b - s.birth_base[lo]);
     const uint32_t di = n_surv + b;
+    if (si >= se.cap) continue;
     int cell = 0;
     real pos;
     if constexpr (std::is_same<P, P32>::value) {

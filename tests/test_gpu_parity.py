@@ -166,3 +166,45 @@ def test_fp64_free_running_20_steps(fspic, oracle_mod, name, wl):
         orc.step(1)
         compare(sim, orc, False, "%s step %d" % (name, k))
     sim.close()
+
+
+def test_diagnostics_match_oracle(fspic, oracle_mod):
+    """Time averages of the node weights and potential, the EEDF histogram (bin decided in
+    FP64 from the same velocities: exact counts), the wall field / surface charge and the
+    physical-unit densities, after 30 FP64 steps of the small bounded discharge."""
+    wl = small_rf(avg_start=10, diag_every=5)
+    sim = fspic.Simulation(wl, "fp64")
+    orc = oracle_mod.Oracle(wl)
+    orc.load()
+    sim.step(30)
+    orc.step(30)
+    t = orc.tallies()
+    g = sim.diagnostics()
+    assert g.acc_count == t.acc_count == 20
+    assert g.eedf_samples == t.eedf_samples == 4
+    assert np.array_equal(sim.grid("eedf"), orc.grid("eedf"))
+    for name in ("acc_w_e", "acc_w_i"):
+        a, b = sim.grid(name), orc.grid(name)
+        assert np.max(np.abs(a - b)) <= 1e-12 * b.max()
+    a, b = sim.grid("acc_phi"), orc.grid("acc_phi")
+    assert np.max(np.abs(a - b)) <= 1e-10 * np.abs(b).max()
+    e_o = orc.grid("E")
+    e_g = sim.grid("E")
+    assert np.max(np.abs(e_g - e_o)) <= 1e-10 * np.abs(e_o).max()
+    assert g.surface_charge[0] == pytest.approx(e_o[0], rel=1e-10, abs=1e-10)
+    assert g.surface_charge[1] == pytest.approx(-e_o[-1], rel=1e-10, abs=1e-10)
+    d = sim.derived[0]
+    ne = sim.density("n_e", kind=0)
+    ref = orc.grid("w_e") * d.weight_per_area / d.dx
+    ref[0] *= 2
+    ref[-1] *= 2
+    assert np.allclose(ne, ref, rtol=1e-12, atol=1e-6 * ref.max())
+    ni_avg = sim.density("n_i", kind=1)
+    ref = orc.grid("acc_w_i") / 20 * d.weight_per_area / d.dx
+    ref[0] *= 2
+    ref[-1] *= 2
+    assert np.allclose(ni_avg, ref, rtol=1e-12, atol=1e-6 * ref.max())
+    phi = sim.density("phi", kind=1)
+    assert np.allclose(phi, orc.grid("acc_phi") / 20 * d.phi_scale, rtol=1e-9,
+                       atol=1e-9 * np.abs(phi).max())
+    sim.close()
