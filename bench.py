@@ -51,13 +51,13 @@ def read_traffic(precision):
 
 
 def run_path(fs, torch, wls, precision, steps, warmup, graph_k=50, profile_steps=20,
-             tuning=None):
-    sim = fs.Simulation(wls, precision, tuning=tuning)
+             tuning=None, cap_factor=1.5):
+    sim = fs.Simulation(wls, precision, tuning=tuning, cap_factor=cap_factor)
     stream = sim.stream
     sim.set_graph(graph_k)
     sim.step(warmup)
     sim.sync()
-    nd = len(wls)
+    nd = len(sim.workloads)
     ps0 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--path-steps", type=int, default=400)
     ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--mode", choices=["bench", "profile", "copy"], default="bench",
+                    help="profile: only the headline path, for rocprofv3; copy: a plain "
+                         "device copy of known size that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a discharge (or a batch of "
@@ -139,7 +142,21 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.mode == "copy":
+        n = 1 << 28  # 1 GiB of float32, read once and written once per copy
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
     large = workloads.large_c3()
+    if args.mode == "profile":
+        r = run_path(fs, torch, large, "fp32_offset", args.steps, args.warmup, profile_steps=5)
+        print(json.dumps({"mode": "profile", "value": r["value"], "steps": args.steps,
+                          "particle_steps": r["particle_steps"], "kernel_ms": r["kernel_ms"]}))
+        return
     print("bench: FP32 cell+offset, large discharge, %d steps" % args.steps, file=sys.stderr,
           flush=True)
     head = run_path(fs, torch, large, "fp32_offset", args.steps, args.warmup)
@@ -151,7 +168,10 @@ def main():
                          "steps": args.path_steps, "kernel_ms": r64["kernel_ms"]}
         print("bench: batched scan", file=sys.stderr, flush=True)
         batch = workloads.batched_c4(scale=args.batched_scale)
-        rb = run_path(fs, torch, batch, "fp32_offset", args.path_steps, args.warmup)
+        # the hottest discharges of the scan (55-95 Pa, 400-490 V, < 2.5 cm) more than
+        # double their ion count within a few hundred steps
+        rb = run_path(fs, torch, batch, "fp32_offset", args.path_steps, args.warmup,
+                      cap_factor=4.0)
         paths["batched"] = {"value": rb["value"], "ms_per_step": rb["ms_per_step"],
                             "steps": args.path_steps, "discharges": len(batch),
                             "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"]}

@@ -173,7 +173,7 @@ int pic_get_state(pic_sim* sim, int discharge, pic_state* st);        /* syncs *
 int pic_set_state(pic_sim* sim, int discharge, const pic_state* st);  /* syncs */
 
 /* Per-phase kernel timing (eager launches bracketed by HIP events on the sim's stream).
-   Phases: 0 combine, 1 solve, 2 hist, 3 scan, 4 main, 5 finalize. */
+   Phases: 0 combine, 1 solve, 2 hist, 3 scan, 4 main, 5 collide, 6 finalize. */
 int pic_profile(pic_sim* sim, int enable);
 int pic_profile_read(pic_sim* sim, double* ms_total, uint64_t* launches, int n_phases);
 

@@ -26,7 +26,7 @@ LOAD = {"random": 0, "quiet_langmuir": 1}
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_CAPACITY", -3: "PIC_ERR_DEVICE",
           -4: "PIC_ERR_NONFINITE", -5: "PIC_ERR_ID_OVERFLOW", -6: "PIC_ERR_STATE",
           -7: "PIC_ERR_WORKSPACE"}
-PHASES = ("combine", "solve", "hist", "scan", "main", "finalize")
+PHASES = ("combine", "solve", "hist", "scan", "main", "collide", "finalize")
 
 U32, U64, I32, F64, P = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
                          ctypes.c_void_p)

@@ -17,7 +17,7 @@ namespace {
 
 thread_local std::string g_init_error;
 
-constexpr int kPhases = 6;
+constexpr int kPhases = 7;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -167,9 +167,13 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.base = cv.take<uint32_t>(N);
       S.far_dest = cv.take<uint32_t>(cap);
       const int ntt = tc.n_tiles + tc.n_tail;
+      S.cand = cv.take<uint4>(cap);
+      S.cand_cnt = cv.take<uint32_t>(ntt);
       S.birth_cnt = cv.take<uint32_t>(ntt);
       S.tile_first = cv.take<uint32_t>(ntt);
-      S.birth_base = cv.take<uint32_t>(ntt + 1);
+      // births of both species are ranked over the electron tiles
+      const int ntt_e = pl->tiles[2 * d].n_tiles + pl->tiles[2 * d].n_tail;
+      S.birth_base = cv.take<uint32_t>(std::max(ntt, ntt_e) + 1);
       S.absorbed = cv.take<unsigned long long>(2);
       S.absorbed_energy = cv.take<double>(2);
       S.births = cv.take<unsigned long long>(1);
@@ -245,7 +249,7 @@ struct pic_sim {
   hipStream_t cap_stream = nullptr;
   // profiling
   bool prof = false;
-  hipEvent_t ev[kPhases + 1] = {};
+  hipEvent_t ev[2 * kPhases] = {};
   double ms[kPhases] = {};
   uint64_t cnt[kPhases] = {};
 };
@@ -317,28 +321,24 @@ static int step_once(pic_sim* sim, hipStream_t st) {
     launch_hist(li, d, st);
     launch_scan(li, d, st);
     launch_main(li, d, st);
+    launch_collide(li, d, st);
     launch_finalize(li, d, st);
     return launch_check(sim, "step launch");
   }
-  HIPCHECK(sim, hipEventRecord(sim->ev[0], st));
-  launch_combine(li, d, st);
-  HIPCHECK(sim, hipEventRecord(sim->ev[1], st));
-  launch_solve(li, d, 0, st);
-  HIPCHECK(sim, hipEventRecord(sim->ev[2], st));
-  launch_hist(li, d, st);
-  HIPCHECK(sim, hipEventRecord(sim->ev[3], st));
-  launch_scan(li, d, st);
-  HIPCHECK(sim, hipEventRecord(sim->ev[4], st));
-  launch_main(li, d, st);
-  HIPCHECK(sim, hipEventRecord(sim->ev[5], st));
-  launch_finalize(li, d, st);
-  HIPCHECK(sim, hipEventRecord(sim->ev[6], st));
+  hipEvent_t* ev = sim->ev;
+  launch_combine(li, d, st, ev[0], ev[1]);
+  launch_solve(li, d, 0, st, ev[2], ev[3]);
+  launch_hist(li, d, st, ev[4], ev[5]);
+  launch_scan(li, d, st, ev[6], ev[7]);
+  launch_main(li, d, st, ev[8], ev[9]);
+  launch_collide(li, d, st, ev[10], ev[11]);
+  launch_finalize(li, d, st, ev[12], ev[13]);
   int rc = launch_check(sim, "step launch");
   if (rc != PIC_OK) return rc;
-  HIPCHECK(sim, hipEventSynchronize(sim->ev[6]));
+  HIPCHECK(sim, hipEventSynchronize(ev[2 * kPhases - 1]));
   for (int p = 0; p < kPhases; ++p) {
     float ms = 0.0f;
-    HIPCHECK(sim, hipEventElapsedTime(&ms, sim->ev[p], sim->ev[p + 1]));
+    HIPCHECK(sim, hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
     sim->ms[p] += ms;
     sim->cnt[p] += 1;
   }
@@ -776,7 +776,7 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
 extern "C" int pic_profile(pic_sim* sim, int enable) {
   if (!sim) return PIC_ERR_STATE;
   if (enable && !sim->ev[0])
-    for (int i = 0; i <= kPhases; ++i) HIPCHECK(sim, hipEventCreate(&sim->ev[i]));
+    for (int i = 0; i < 2 * kPhases; ++i) HIPCHECK(sim, hipEventCreate(&sim->ev[i]));
   sim->prof = enable != 0;
   for (int i = 0; i < kPhases; ++i) {
     sim->ms[i] = 0.0;
@@ -799,7 +799,7 @@ extern "C" void pic_free(pic_sim* sim) {
   if (sim->stream) hipStreamSynchronize(sim->stream);
   if (sim->exec) hipGraphExecDestroy(sim->exec);
   if (sim->cap_stream) hipStreamDestroy(sim->cap_stream);
-  for (int i = 0; i <= kPhases; ++i)
+  for (int i = 0; i < 2 * kPhases; ++i)
     if (sim->ev[i]) hipEventDestroy(sim->ev[i]);
   delete sim;
 }

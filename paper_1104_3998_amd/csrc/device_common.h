@@ -29,16 +29,15 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo_a = 0xD2511F53u * c0;
-    const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo_b = 0xCD9E8D57u * c2;
-    const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi_b ^ c1 ^ k0;
-    const uint32_t n2 = hi_a ^ c3 ^ k1;
+    // one 32x32->64 product per multiplier (a single v_mad_u64_u32)
+    const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t n0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
     c0 = n0;
-    c1 = lo_b;
+    c1 = static_cast<uint32_t>(pb);
     c2 = n2;
-    c3 = lo_a;
+    c3 = static_cast<uint32_t>(pa);
   }
   return make_uint4(c0, c1, c2, c3);
 }
@@ -248,6 +247,34 @@ __device__ __forceinline__ int window_slot(const SpeciesDev& s, int t, int d) {
     if (k < 0) k += s.n_cells;
   }
   return (k >= 0 && k < s.W) ? k : -1;
+}
+
+// ------------------------------------------------------------------------------------
+// Wave-level helpers.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Mask of the active lanes whose key equals this lane's key (keys < 2^nbits); valid for
+// active lanes.  One ballot per key bit, so the cost does not depend on how many lanes
+// share a key.
+__device__ __forceinline__ unsigned long long match_key(int key, bool act, int nbits) {
+  unsigned long long m = __ballot(act);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = act && ((key >> b) & 1);
+    const unsigned long long mb = __ballot(bit);
+    m &= bit ? mb : ~mb;
+  }
+  return m;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = x + __shfl_xor(x, o, 64);
+  return x;
 }
 
 // ------------------------------------------------------------------------------------

@@ -26,12 +26,21 @@ struct LaunchInfo {
 };
 
 // Step kernels (kernels_step.hip).  `sim` points at the SimDev copy in device memory.
-void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
-void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st);
-void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
-void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
-void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
-void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st);
+// With events e0 / e1, they are recorded at the start / end of the phase's kernels.
+void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st,
+                  hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st,
+                    hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st,
+                     hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Set-up kernels (kernels_setup.hip).
 void launch_load(const LaunchInfo& li, const SimDev* sim, int dst_buf, hipStream_t st);

@@ -3,10 +3,11 @@
 //   k_combine   node weights w_s = sum of the tile deposit windows + far/birth deposits
 //   k_solve     Poisson + field on the nodes (Sec. 3.5), one workgroup per discharge
 //   k_hist      per-tile LDS histogram of the post-push cells (sort pre-pass, Sec. 3.7)
-//   k_scan      per-(tile, cell) output offsets; far movers ranked (one workgroup per
-//               discharge and species)
-//   k_main      push + gather (Sec. 3.6), walls (Sec. 2), null-collision MCC (Sec. 3.8),
-//               stable scatter into the sorted output, LDS deposit (Sec. 3.4)
+//   k_scan_cells / k_scan_base
+//               per-(tile, cell) output offsets; far movers ranked
+//   k_main      push + gather (Sec. 3.6), walls (Sec. 2), stable scatter into the sorted
+//               output, LDS deposit (Sec. 3.4), null-collision candidate test
+//   k_collide   MCC of the candidates (Sec. 3.8), births staged in parent order
 //   k_finalize  births appended in parent order, counters, step advance
 //
 // A tile is the set of particles of C consecutive cells (the paper puts one sorting cell
@@ -14,6 +15,8 @@
 // cells of its cells except for rare far movers, so the stable counting sort needs
 // only a (C + 2D)-slot histogram per tile.  No global float atomics are used on the
 // bulk path; far movers and births (a small fraction) add into a per-node FP64 array.
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 #include "device_common.h"
@@ -298,7 +301,10 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
 
 // ====================================================================================
 // k_hist: post-push cell histogram of each tile over its window (sort pre-pass).
-// Particles leaving the window (and the unsorted births tail) go to the far list.
+// Each wave keeps its own LDS histogram; lanes with the same slot are grouped with
+// ballots and one leader adds the group's count, so there is no atomic traffic on the
+// crowded slots.  Particles leaving the window (and the unsorted births tail) go to the
+// far list.  Two particles per thread per pass keep more loads in flight.
 // ====================================================================================
 template <class P>
 __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
@@ -310,50 +316,82 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   const int p = static_cast<int>(*sim.step & 1ull);
   const TileRange r = tile_range(s, tt.y, p);
   __shared__ real Elds[kMaxCellsPerTile + 1];
-  __shared__ uint32_t h[kMaxWindow];
+  __shared__ uint32_t h[kWaves][kMaxWindow];
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const unsigned long long lt = lanes_below();
   const real* E = std::is_same<P, P32>::value ? reinterpret_cast<const real*>(dd.E32)
                                                : reinterpret_cast<const real*>(dd.E64);
   load_field_window<real>(s, E, r, Elds);
-  for (int k = threadIdx.x; k < s.W; k += blockDim.x) h[k] = 0u;
+  const int W = s.W;
+  for (int k = tid; k < kWaves * W; k += kWG) h[k / W][k % W] = 0u;
+  int nbits = 0;
+  while ((1 << nbits) < W) ++nbits;
   __syncthreads();
   void* const* in = s.fld[p];
-  for (uint32_t i = r.lo + threadIdx.x; i < r.hi; i += blockDim.x) {
-    Part<P> q;
-    q.load(in, i);
-    int d;
-    real pos, vxn;
-    const int st = push_particle<P>(s, dd, Elds, r, q, d, pos, vxn);
-    if (st != 0) continue;
-    const int k = r.tail ? -1 : window_slot(s, tt.y, d);
-    if (k >= 0) {
-      atomicAdd(&h[k], 1u);
-    } else {
-      const uint32_t e = atomicAdd(s.far_count, 1u);
-      if (e < s.far_cap) {
-        s.far_list[e] = make_uint4(static_cast<uint32_t>(d), i, static_cast<uint32_t>(tt.y), 0u);
-        atomicAdd(&s.far_cell_cnt[d], 1u);
+  for (uint32_t b = r.lo; b < r.hi; b += 2 * kWG) {
+    Part<P> q[2];
+    bool valid[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t i = b + u * kWG + tid;
+      valid[u] = i < r.hi;
+      if (valid[u]) q[u].load(in, i);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t i = b + u * kWG + tid;
+      int st = 4, d = 0;
+      real pos, vxn;
+      if (valid[u]) st = push_particle<P>(s, dd, Elds, r, q[u], d, pos, vxn);
+      const int k = (st == 0 && !r.tail) ? window_slot(s, tt.y, d) : -1;
+      const bool near = k >= 0;
+      const unsigned long long m = match_key(k, near, nbits);
+      if (near && __popcll(m & lt) == 0) h[wv][k] += static_cast<uint32_t>(__popcll(m));
+      if (st == 0 && !near) {
+        const uint32_t e = atomicAdd(s.far_count, 1u);
+        if (e < s.far_cap) {
+          s.far_list[e] = make_uint4(static_cast<uint32_t>(d), i, static_cast<uint32_t>(tt.y), 0u);
+          atomicAdd(&s.far_cell_cnt[d], 1u);
+        }
       }
     }
   }
   __syncthreads();
   if (!r.tail)
-    for (int k = threadIdx.x; k < s.W; k += blockDim.x)
-      s.hist[static_cast<size_t>(tt.y) * s.W + k] = h[k];
+    for (int k = tid; k < W; k += kWG)
+      s.hist[static_cast<size_t>(tt.y) * W + k] = h[0][k] + h[1][k] + h[2][k] + h[3][k];
 }
 
 // ====================================================================================
-// k_scan: one workgroup per (discharge, species).  Output order = stable sort of the
-// survivors by cell (ties in input order).  For cell c:
+// Output offsets.  Output order = stable sort of the survivors by cell (ties in input
+// order).  For cell c:
 //   count(c) = sum of the covering tiles' histogram entries + far movers into c,
 //   base(c)  = exclusive scan of count;
 //   a tile t's particles in c start at base(c) + (far movers into c from tiles < t)
 //              + (histogram entries of the covering tiles < t);
 //   a far mover from tile u starts at base(c) + (its rank by index among the far movers
 //              into c) + (histogram entries of the covering tiles < u).
+// k_scan_cells does the per-cell part across the whole chip; k_scan_base (one workgroup
+// per discharge and species) scans over cells and places the far movers.
 // ====================================================================================
 constexpr uint32_t kMaxFarGroup = 8192;
 
-__global__ __launch_bounds__(kSolveWG) void k_scan(const SimDev* __restrict__ simp) {
+__global__ __launch_bounds__(256) void k_scan_cells(const SimDev* __restrict__ simp) {
+  const SimDev& sim = *simp;
+  const SpeciesDev& s = sim.sp[blockIdx.y];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= s.n_cells) return;
+  const int W = s.W;
+  uint32_t run = 0;
+  for_covering(s, c, W, [&](int t, int k) {
+    const size_t o = static_cast<size_t>(t) * W + k;
+    s.tilerel[o] = run;
+    run += s.hist[o];
+  });
+  s.base[c] = run + s.far_cell_cnt[c];
+}
+
+__global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
   const SpeciesDev& s = sim.sp[blockIdx.x];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
@@ -362,54 +400,54 @@ __global__ __launch_bounds__(kSolveWG) void k_scan(const SimDev* __restrict__ si
   const uint32_t fc = *s.far_count;
   const uint32_t F = fc < s.far_cap ? fc : s.far_cap;
   if (threadIdx.x == 0 && fc > s.far_cap) atomicOr(sim.error, kErrFarOverflow);
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    s.far_fill[c] = 0u;
-    s.far_base[c] = s.far_cell_cnt[c];
-  }
-  __syncthreads();
-  array_exclusive_scan(s.far_base, N, lds);
-  for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
-    const uint4 v = s.far_list[e];
-    if (v.x >= static_cast<uint32_t>(N)) {
-      atomicOr(sim.error, kErrState);
-      continue;
-    }
-    const uint32_t pos = s.far_base[v.x] + atomicAdd(&s.far_fill[v.x], 1u);
-    if (pos < F) s.far_grouped[pos] = v;
-  }
-  __threadfence();
-  __syncthreads();
-  for (int c = threadIdx.x; c < N; c += blockDim.x) {
-    const uint32_t g = s.far_cell_cnt[c];
-    const uint32_t gb = s.far_base[c];
-    if (g > kMaxFarGroup) atomicOr(sim.error, kErrFarGroup);
-    const uint32_t gl = g > kMaxFarGroup ? 0u : g;
-    uint32_t run = 0;
-    for_covering(s, c, W, [&](int t, int k) {
-      uint32_t fb = 0;
-      for (uint32_t m = 0; m < gl; ++m) fb += s.far_grouped[gb + m].z < static_cast<uint32_t>(t);
-      const size_t o = static_cast<size_t>(t) * W + k;
-      s.tilerel[o] = run + fb;
-      run += s.hist[o];
-    });
-    s.base[c] = run + g;
-  }
-  __syncthreads();
   const uint32_t n_surv = array_exclusive_scan(s.base, N, lds);
-  for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
-    const uint4 v = s.far_grouped[e];
-    if (v.x >= static_cast<uint32_t>(N) || v.y >= s.cap) continue;
-    const int c = static_cast<int>(v.x);
-    const uint32_t g = s.far_cell_cnt[c];
-    const uint32_t gb = s.far_base[c];
-    if (g > kMaxFarGroup) continue;
-    uint32_t rank = 0;
-    for (uint32_t m = 0; m < g; ++m) rank += s.far_grouped[gb + m].y < v.y;
-    uint32_t nb = 0;
-    for_covering(s, c, W, [&](int t, int k) {
-      if (static_cast<uint32_t>(t) < v.z) nb += s.hist[static_cast<size_t>(t) * W + k];
-    });
-    s.far_dest[v.y] = s.base[c] + rank + nb;
+  if (F > 0) {
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      s.far_fill[c] = 0u;
+      s.far_base[c] = s.far_cell_cnt[c];
+    }
+    array_exclusive_scan(s.far_base, N, lds);
+    for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
+      const uint4 v = s.far_list[e];
+      if (v.x >= static_cast<uint32_t>(N)) {
+        atomicOr(sim.error, kErrState);
+        continue;
+      }
+      const uint32_t pos = s.far_base[v.x] + atomicAdd(&s.far_fill[v.x], 1u);
+      if (pos < F) s.far_grouped[pos] = v;
+    }
+    __threadfence();
+    __syncthreads();
+    // tiles' offsets in cells that receive far movers from lower tiles
+    for (int c = threadIdx.x; c < N; c += blockDim.x) {
+      const uint32_t g = s.far_cell_cnt[c];
+      if (g == 0u) continue;
+      if (g > kMaxFarGroup) {
+        atomicOr(sim.error, kErrFarGroup);
+        continue;
+      }
+      const uint32_t gb = s.far_base[c];
+      for_covering(s, c, W, [&](int t, int k) {
+        uint32_t fb = 0;
+        for (uint32_t m = 0; m < g; ++m) fb += s.far_grouped[gb + m].z < static_cast<uint32_t>(t);
+        s.tilerel[static_cast<size_t>(t) * W + k] += fb;
+      });
+    }
+    for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
+      const uint4 v = s.far_grouped[e];
+      if (v.x >= static_cast<uint32_t>(N) || v.y >= s.cap) continue;
+      const int c = static_cast<int>(v.x);
+      const uint32_t g = s.far_cell_cnt[c];
+      const uint32_t gb = s.far_base[c];
+      if (g > kMaxFarGroup) continue;
+      uint32_t rank = 0;
+      for (uint32_t m = 0; m < g; ++m) rank += s.far_grouped[gb + m].y < v.y;
+      uint32_t nb = 0;
+      for_covering(s, c, W, [&](int t, int k) {
+        if (static_cast<uint32_t>(t) < v.z) nb += s.hist[static_cast<size_t>(t) * W + k];
+      });
+      s.far_dest[v.y] = s.base[c] + rank + nb;
+    }
   }
   uint32_t* cs = s.cell_start + q * (N + 1);
   for (int c = threadIdx.x; c < N; c += blockDim.x) cs[c] = s.base[c];
@@ -422,26 +460,20 @@ __global__ __launch_bounds__(kSolveWG) void k_scan(const SimDev* __restrict__ si
 // ====================================================================================
 // k_main: the fused particle pass of one tile.
 // ====================================================================================
+constexpr int kReduceSlots = 4;     // up to this many distinct slots a wave reduces in
+                                    // registers; more, and it adds with LDS atomics
+constexpr uint32_t kNoDest = 0xFFFFFFFFu;
+
 template <class P>
 struct MainShared {
   using real = typename Part<P>::real;
   real Elds[kMaxCellsPerTile + 1];
-  real dep[kMaxWindow + 1];
   uint32_t off[kMaxWindow];
   uint32_t wcnt[kWaves][kMaxWindow];
-  real sv[3][kWG];     // velocities after the push (updated by collisions)
-  real spos[kWG];      // new offset (FP32) or x (FP64)
-  int sd[kWG];         // destination cell
-  uint32_t sid[kWG];
-  uint32_t sw1[kWG], sw2[kWG];
-  int sborn[kWG];
-  real sbv[6][kWG];    // secondary electron and new ion velocities
-  int queue[kWG];
-  int qn;
-  uint32_t wb[kWaves + 1];
+  real dep[kWaves][kMaxWindow + 1];
+  uint32_t cq[kWaves + 1];   // per-wave candidate append position; [kWaves] = tile total
   uint32_t eedf[kMaxEedfBins + 1];
   uint32_t abs_cnt[2];
-  uint32_t coll[3];
   double abs_e[2];
 };
 
@@ -498,11 +530,9 @@ __device__ int collide(const SpeciesDev& s, uint32_t id, uint32_t step, uint32_t
       v[1] = static_cast<real>(vn * n1);
       v[2] = static_cast<real>(vn * n2);
     } else {
-      const uint4 b2 = philox(id, step, 2u, 0u, s.key0, s.key1);
-      const uint4 b3 = philox(id, step, 3u, 0u, s.key0, s.key1);
-      const uint4 b4 = philox(id, step, 4u, 0u, s.key0, s.key1);
-      const uint4 b5 = philox(id, step, 5u, 0u, s.key0, s.key1);
+      // draws taken one block at a time (blocks 2..5) to keep few values live
       const double er = eps - kIonEv;
+      const uint4 b2 = philox(id, step, 2u, 0u, s.key0, s.key1);
       const double es = u53(b2.x, b2.y) * er;
       const double epr = er - es;
       double n0, n1, n2;
@@ -511,16 +541,16 @@ __device__ int collide(const SpeciesDev& s, uint32_t id, uint32_t step, uint32_t
       v[0] = static_cast<real>(vp * n0);
       v[1] = static_cast<real>(vp * n1);
       v[2] = static_cast<real>(vp * n2);
-      direction64(b3, n0, n1, n2);
+      direction64(philox(id, step, 3u, 0u, s.key0, s.key1), n0, n1, n2);
       const double vsm = sqrt(es / s.energy_c);
       vs[0] = static_cast<real>(vsm * n0);
       vs[1] = static_cast<real>(vsm * n1);
       vs[2] = static_cast<real>(vsm * n2);
       double z0, z1, z2, z3;
-      normals64(b4, z0, z1);
-      normals64(b5, z2, z3);
+      normals64(philox(id, step, 4u, 0u, s.key0, s.key1), z0, z1);
       vi[0] = static_cast<real>(s.vth_gas * z0);
       vi[1] = static_cast<real>(s.vth_gas * z1);
+      normals64(philox(id, step, 5u, 0u, s.key0, s.key1), z2, z3);
       vi[2] = static_cast<real>(s.vth_gas * z2);
     }
     return ch;
@@ -572,6 +602,21 @@ __device__ __forceinline__ void far_deposit(const SpeciesDev& s, int d,
   atomicAdd(&s.far_w[dn], f);
 }
 
+// Weights of a particle's deposit onto the two nodes of its cell (Sec. 3.4).
+template <class P>
+__device__ __forceinline__ void deposit_weights(typename Part<P>::real pos,
+                                                typename Part<P>::real& w0,
+                                                typename Part<P>::real& w1) {
+  if constexpr (std::is_same<P, P32>::value) {
+    w0 = 1.0f - pos;
+    w1 = pos;
+  } else {
+    const double f = pos - floor(pos);
+    w0 = 1.0 - f;
+    w1 = f;
+  }
+}
+
 template <class P>
 __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
@@ -586,7 +631,7 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   const int tile = tt.y;
   __shared__ MainShared<P> sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const unsigned long long lt = lanes_below();
   const bool eedf_on = s.sp == 0 && diag_step(dd, step);
   const bool far_ok = (*sim.error & kErrFarOverflow) == 0u;
   const uint32_t n_out = s.n_sorted[pq];
@@ -604,14 +649,12 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
                     ? s.base[c] + s.tilerel[static_cast<size_t>(tile) * W + k]
                     : 0u;
   }
-  for (int k = tid; k <= W; k += kWG) sh.dep[k] = real(0);
+  for (int k = tid; k < kWaves * (W + 1); k += kWG) sh.dep[k / (W + 1)][k % (W + 1)] = real(0);
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG) sh.eedf[k] = 0u;
   if (tid == 0) {
-    sh.qn = 0;
-    sh.wb[kWaves] = 0u;
+    sh.cq[kWaves] = 0u;
     sh.abs_cnt[0] = sh.abs_cnt[1] = 0u;
-    sh.coll[0] = sh.coll[1] = sh.coll[2] = 0u;
     sh.abs_e[0] = sh.abs_e[1] = 0.0;
   }
   int nbits = 0;
@@ -619,94 +662,51 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   __syncthreads();
   void* const* in = s.fld[p];
   void* const* out = s.fld[pq];
-  const SpeciesDev* ion = s.sp == 0 ? &sim.sp[tt.x + 1] : nullptr;
+  Part<P> nxt;
+  bool nxt_ok = r.lo + tid < r.hi;
+  if (nxt_ok) nxt.load(in, r.lo + tid);
   for (uint32_t base_i = r.lo; base_i < r.hi; base_i += kWG) {
     const uint32_t i = base_i + tid;
-    const bool valid = i < r.hi;
-    for (int k = tid; k < kWaves * W; k += kWG) sh.wcnt[k / W][k % W] = 0u;
-    Part<P> q;
+    const bool valid = nxt_ok;
+    const Part<P> q = nxt;
+    {  // issue the next chunk's loads before working on this one
+      const uint32_t ni = i + kWG;
+      nxt_ok = ni < r.hi;
+      if (nxt_ok) nxt.load(in, ni);
+    }
     int st = 4, d = 0;
     real pos = real(0), vxn = real(0);
-    if (valid) {
-      q.load(in, i);
-      st = push_particle<P>(s, dd, sh.Elds, r, q, d, pos, vxn);
+    if (valid) st = push_particle<P>(s, dd, sh.Elds, r, q, d, pos, vxn);
+    if (valid && (eedf_on || st == 1 || st == 2)) {
       const double v2 = static_cast<double>(vxn) * static_cast<double>(vxn) +
                         static_cast<double>(q.vy) * static_cast<double>(q.vy) +
                         static_cast<double>(q.vz) * static_cast<double>(q.vz);
       if (eedf_on && st != 3) {
-        const double eps = s.energy_c * v2;
-        const double b = floor(eps * dd.eedf_inv_width);
+        const double b = floor(s.energy_c * v2 * dd.eedf_inv_width);
         const int bin = b >= static_cast<double>(dd.eedf_bins) ? dd.eedf_bins : static_cast<int>(b);
         atomicAdd(&sh.eedf[bin], 1u);
       }
       if (st == 1 || st == 2) {
         atomicAdd(&sh.abs_cnt[st - 1], 1u);
         atomicAdd(&sh.abs_e[st - 1], s.energy_c * v2);
-      } else if (st == 3) {
-        atomicOr(sim.error, kErrState);
-      } else {
-        sh.sv[0][tid] = vxn;
-        sh.sv[1][tid] = q.vy;
-        sh.sv[2][tid] = q.vz;
-        sh.sborn[tid] = 0;
-        if (s.t0 != 0u) {
-          const uint4 b0 = philox(q.id, step32, 0u, 0u, s.key0, s.key1);
-          if (b0.x < s.t0) {
-            sh.sid[tid] = q.id;
-            sh.sw1[tid] = b0.y;
-            sh.sw2[tid] = b0.z;
-            sh.sd[tid] = d;
-            sh.spos[tid] = pos;
-            const int slot = atomicAdd(&sh.qn, 1);
-            sh.queue[slot] = tid;
-          }
-        }
       }
     }
-    __syncthreads();  // B1: candidate queue complete
-    const int qn = sh.qn;
-    for (int qi = tid; qi < qn; qi += kWG) {
-      const int L = sh.queue[qi];
-      real v[3] = {sh.sv[0][L], sh.sv[1][L], sh.sv[2][L]};
-      real vs[3], vi[3];
-      const int ch = collide<P>(s, sh.sid[L], step32, sh.sw1[L], sh.sw2[L], v, vs, vi);
-      if (ch > 0) {
-        atomicAdd(&sh.coll[ch - 1], 1u);
-        sh.sv[0][L] = v[0];
-        sh.sv[1][L] = v[1];
-        sh.sv[2][L] = v[2];
-        if (s.sp == 0 && ch == 3) {
-          sh.sborn[L] = 1;
-          for (int a = 0; a < 3; ++a) {
-            sh.sbv[a][L] = vs[a];
-            sh.sbv[3 + a][L] = vi[a];
-          }
-        }
-      }
-    }
-    __syncthreads();  // B2: collisions done
-    real vy = q.vy, vz = q.vz;
-    bool born = false;
-    if (st == 0) {
-      vxn = sh.sv[0][tid];
-      vy = sh.sv[1][tid];
-      vz = sh.sv[2][tid];
-      born = sh.sborn[tid] != 0;
+    if (st == 3) atomicOr(sim.error, kErrState);
+    bool cand = false;
+    uint4 b0 = make_uint4(0u, 0u, 0u, 0u);
+    if (st == 0 && s.t0 != 0u) {
+      b0 = philox(q.id, step32, 0u, 0u, s.key0, s.key1);
+      cand = b0.x < s.t0;
     }
     const int k = (st == 0 && !r.tail) ? window_slot(s, tile, d) : -1;
     const bool near = k >= 0;
-    unsigned long long m = __ballot(near);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = near && ((k >> b) & 1);
-      const unsigned long long mb = __ballot(bit);
-      m &= (near && ((k >> b) & 1)) ? mb : ~mb;
-    }
+    const unsigned long long m = match_key(k, near, nbits);
     const int rank = __popcll(m & lt);
+    for (int kk = lane; kk < W; kk += 64) sh.wcnt[wv][kk] = 0u;
     if (near && rank == 0) sh.wcnt[wv][k] = static_cast<uint32_t>(__popcll(m));
-    const unsigned long long bm = __ballot(born);
-    const int brank_w = __popcll(bm & lt);
-    if (lane == 0) sh.wb[wv] = static_cast<uint32_t>(__popcll(bm));
-    __syncthreads();  // B3: per-wave counts
+    const unsigned long long cm = __ballot(cand);
+    if (lane == 0) sh.cq[wv] = static_cast<uint32_t>(__popcll(cm));
+    __syncthreads();  // per-wave slot and candidate counts written
     for (int kk = tid; kk < W; kk += kWG) {
       uint32_t run = sh.off[kk];
       for (int w = 0; w < kWaves; ++w) {
@@ -717,15 +717,15 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       sh.off[kk] = run;
     }
     if (tid == kWG - 1) {
-      uint32_t run = sh.wb[kWaves];
+      uint32_t run = sh.cq[kWaves];
       for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = sh.wb[w];
-        sh.wb[w] = run;
+        const uint32_t c = sh.cq[w];
+        sh.cq[w] = run;
         run += c;
       }
-      sh.wb[kWaves] = run;
+      sh.cq[kWaves] = run;
     }
-    __syncthreads();  // B4: offsets known
+    __syncthreads();  // output offsets and queue positions known
     if (st == 0) {
       uint32_t dst;
       bool ok;
@@ -733,69 +733,153 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
         dst = sh.wcnt[wv][k] + static_cast<uint32_t>(rank);
         ok = true;
       } else {
-        dst = far_ok ? s.far_dest[i] : 0u;
         ok = far_ok;
+        dst = ok ? s.far_dest[i] : 0u;
       }
       if (ok && dst >= n_out) {
         atomicOr(sim.error, kErrState);
         ok = false;
       }
-      if (ok) store_record<P>(out, dst, d, pos, vxn, vy, vz, q.id);
-      if (near) {
-        if constexpr (std::is_same<P, P32>::value) {
-          atomicAdd(&sh.dep[k], 1.0f - pos);
-          atomicAdd(&sh.dep[k + 1], pos);
-        } else {
-          const double f = pos - floor(pos);
-          atomicAdd(&sh.dep[k], 1.0 - f);
-          atomicAdd(&sh.dep[k + 1], f);
-        }
-      } else if (ok) {
-        far_deposit<P>(s, d, pos);
+      if (ok) store_record<P>(out, dst, d, pos, vxn, q.vy, q.vz, q.id);
+      if (cand) {  // the tile's candidates, in input order, for k_collide
+        const uint32_t e = r.lo + sh.cq[wv] + static_cast<uint32_t>(__popcll(cm & lt));
+        if (e < s.cap) s.cand[e] = make_uint4(ok ? dst : kNoDest, q.id, b0.y, b0.z);
       }
-      if (born && r.lo + sh.wb[wv] + static_cast<uint32_t>(brank_w) < s.cap) {
-        const uint32_t brank = sh.wb[wv] + static_cast<uint32_t>(brank_w);
-        const uint32_t si = r.lo + brank;
-        store_record<P, false>(s.stage[0], si, d, pos, sh.sbv[0][tid], sh.sbv[1][tid],
-                               sh.sbv[2][tid], 0u);
-        store_record<P, false>(s.stage[1], si, d, pos, sh.sbv[3][tid], sh.sbv[4][tid],
-                               sh.sbv[5][tid], 0u);
-        if (near) {
-          if constexpr (std::is_same<P, P32>::value) {
-            atomicAdd(&sh.dep[k], 1.0f - pos);
-            atomicAdd(&sh.dep[k + 1], pos);
-          } else {
-            const double f = pos - floor(pos);
-            atomicAdd(&sh.dep[k], 1.0 - f);
-            atomicAdd(&sh.dep[k + 1], f);
-          }
-        } else {
-          far_deposit<P>(s, d, pos);
-        }
-        far_deposit<P>(*ion, d, pos);
-      }
+      if (!near && ok) far_deposit<P>(s, d, pos);
     }
-    if (tid == 0) sh.qn = 0;
-    __syncthreads();  // B5: LDS free for the next chunk
+    // deposit of the near particles into this wave's window
+    real w0 = real(0), w1 = real(0);
+    if (near) deposit_weights<P>(pos, w0, w1);
+    const unsigned long long lead = __ballot(near && rank == 0);
+    if (__popcll(lead) <= kReduceSlots) {
+      unsigned long long rem = lead;
+      while (rem) {
+        const int L = __ffsll(static_cast<long long>(rem)) - 1;
+        const int key = __shfl(k, L, 64);
+        const bool mine = near && k == key;
+        const real a = wave_sum<real>(mine ? w0 : real(0));
+        const real b = wave_sum<real>(mine ? w1 : real(0));
+        if (lane == L) {
+          sh.dep[wv][key] += a;
+          sh.dep[wv][key + 1] += b;
+        }
+        rem &= rem - 1ull;
+      }
+    } else if (near) {
+      atomicAdd(&sh.dep[wv][k], w0);
+      atomicAdd(&sh.dep[wv][k + 1], w1);
+    }
   }
+  __syncthreads();
   // tile epilogue
   if (!r.tail) {
     real* part = static_cast<real*>(s.partial) + static_cast<size_t>(tile) * (W + 1);
-    for (int k = tid; k <= W; k += kWG) part[k] = sh.dep[k];
+    for (int k = tid; k <= W; k += kWG) part[k] = sh.dep[0][k] + sh.dep[1][k] + sh.dep[2][k] + sh.dep[3][k];
   }
   if (tid == 0) {
-    s.birth_cnt[tile] = sh.wb[kWaves];
+    s.cand_cnt[tile] = sh.cq[kWaves];
     s.tile_first[tile] = r.lo;
     if (sh.abs_cnt[0]) atomicAdd(&s.absorbed[0], static_cast<unsigned long long>(sh.abs_cnt[0]));
     if (sh.abs_cnt[1]) atomicAdd(&s.absorbed[1], static_cast<unsigned long long>(sh.abs_cnt[1]));
     if (sh.abs_cnt[0]) atomicAdd(&s.absorbed_energy[0], sh.abs_e[0]);
     if (sh.abs_cnt[1]) atomicAdd(&s.absorbed_energy[1], sh.abs_e[1]);
-    for (int c = 0; c < 3; ++c)
-      if (sh.coll[c]) atomicAdd(&s.collisions[c], static_cast<unsigned long long>(sh.coll[c]));
   }
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG)
       if (sh.eedf[k]) atomicAdd(&dd.eedf[k], static_cast<unsigned long long>(sh.eedf[k]));
+}
+
+// ====================================================================================
+// k_collide: modified null-collision MCC (Sec. 3.8, eq. null_collision) of the candidates
+// k_main found (word 0 of the particle's Philox block 0 below floor(P0 2^32)).  One
+// workgroup per tile takes the tile's candidates in input order, 256 at a time, so the
+// collision path runs on full waves.  The particle's record was already scattered to
+// its sorted place; the post-collision velocity is written there.  Births are staged in
+// the order of their parents (= input order) and deposited; k_finalize appends them.
+// ====================================================================================
+template <class P>
+__global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp) {
+  using real = typename Part<P>::real;
+  const SimDev& sim = *simp;
+  const int2 tt = sim.tile_table[blockIdx.x];
+  const SpeciesDev& s = sim.sp[tt.x];
+  const unsigned long long step = *sim.step;
+  const uint32_t step32 = static_cast<uint32_t>(step);
+  const int p = static_cast<int>(step & 1ull), pq = p ^ 1;
+  const int tile = tt.y;
+  const TileRange r = tile_range(s, tile, p);
+  const uint32_t n = s.cand_cnt[tile];
+  __shared__ uint32_t bq[kWaves + 1];
+  __shared__ uint32_t coll[3];
+  __shared__ uint32_t births;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    coll[0] = coll[1] = coll[2] = 0u;
+    births = 0u;
+  }
+  __syncthreads();
+  void* const* out = s.fld[pq];
+  const SpeciesDev* ion = s.sp == 0 ? &sim.sp[tt.x + 1] : nullptr;
+  real* part = static_cast<real*>(s.partial) + static_cast<size_t>(tile) * (s.W + 1);
+  for (uint32_t b = 0; b < n; b += kWG) {
+    const uint32_t e = b + tid;
+    bool born = false;
+    int d = 0;
+    real pos = real(0);
+    real vs[3] = {real(0), real(0), real(0)}, vi[3] = {real(0), real(0), real(0)};
+    const uint4 c = (e < n && r.lo + e < s.cap) ? s.cand[r.lo + e] : make_uint4(kNoDest, 0u, 0u, 0u);
+    const uint32_t dst = c.x;
+    if (dst != kNoDest && dst < s.cap) {
+      if constexpr (std::is_same<P, P32>::value) {
+        d = static_cast<const int*>(out[F32_CELL])[dst];
+        pos = static_cast<const float*>(out[F32_OFF])[dst];
+      } else {
+        pos = static_cast<const double*>(out[F64_X])[dst];
+        d = static_cast<int>(floor(pos));
+      }
+      real v[3];
+      v[0] = static_cast<const real*>(out[F_VX])[dst];
+      v[1] = static_cast<const real*>(out[F_VY])[dst];
+      v[2] = static_cast<const real*>(out[F_VZ])[dst];
+      const int ch = collide<P>(s, c.y, step32, c.z, c.w, v, vs, vi);
+      if (ch > 0) {
+        atomicAdd(&coll[ch - 1], 1u);
+        static_cast<real*>(out[F_VX])[dst] = v[0];
+        static_cast<real*>(out[F_VY])[dst] = v[1];
+        static_cast<real*>(out[F_VZ])[dst] = v[2];
+        born = s.sp == 0 && ch == 3;
+      }
+    }
+    uint32_t total;
+    const uint32_t pre = block_exclusive_scan<uint32_t>(born ? 1u : 0u, bq, total);
+    if (born) {
+      const uint32_t si = r.lo + births + pre;
+      if (si < s.cap) {
+        store_record<P, false>(s.stage[0], si, d, pos, vs[0], vs[1], vs[2], 0u);
+        store_record<P, false>(s.stage[1], si, d, pos, vi[0], vi[1], vi[2], 0u);
+        const int k = r.tail ? -1 : window_slot(s, tile, d);
+        if (k >= 0) {
+          real w0, w1;
+          deposit_weights<P>(pos, w0, w1);
+          atomicAdd(&part[k], w0);
+          atomicAdd(&part[k + 1], w1);
+        } else {
+          far_deposit<P>(s, d, pos);
+        }
+        far_deposit<P>(*ion, d, pos);
+      } else {
+        atomicOr(sim.error, kErrState);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) births += total;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    s.birth_cnt[tile] = births;
+    for (int k = 0; k < 3; ++k)
+      if (coll[k]) atomicAdd(&s.collisions[k], static_cast<unsigned long long>(coll[k]));
+  }
 }
 
 // ====================================================================================
@@ -878,35 +962,58 @@ __global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict_
 }
 
 // ====================================================================================
-// host launchers
+// host launchers.  With events, a launch goes through hipExtLaunchKernelGGL, which
+// records them around the kernel's own execution (used for per-kernel timing).
 // ====================================================================================
-void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
-  dim3 grid((li.max_nodes + 255) / 256, li.n_spec);
-  if (li.fp32) k_combine<float><<<grid, 256, 0, st>>>(sim);
-  else k_combine<double><<<grid, 256, 0, st>>>(sim);
+template <typename K, typename... Args>
+static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0,
+                   hipEvent_t e1, Args... args) {
+  if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+  else kernel<<<grid, block, 0, st>>>(args...);
 }
 
-void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st) {
-  k_solve<<<li.n_ds, kSolveWG, 0, st>>>(sim, init_mode);
+void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
+                    hipEvent_t e1) {
+  const dim3 grid((li.max_nodes + 255) / 256, li.n_spec);
+  if (li.fp32) launch(k_combine<float>, grid, dim3(256), st, e0, e1, sim);
+  else launch(k_combine<double>, grid, dim3(256), st, e0, e1, sim);
 }
 
-void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
-  if (li.fp32) k_hist<P32><<<li.total_tiles, kWG, 0, st>>>(sim);
-  else k_hist<P64><<<li.total_tiles, kWG, 0, st>>>(sim);
+void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st,
+                  hipEvent_t e0, hipEvent_t e1) {
+  launch(k_solve, dim3(li.n_ds), dim3(kSolveWG), st, e0, e1, sim, init_mode);
 }
 
-void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
-  k_scan<<<li.n_spec, kSolveWG, 0, st>>>(sim);
+void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
+                 hipEvent_t e1) {
+  if (li.fp32) launch(k_hist<P32>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+  else launch(k_hist<P64>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
 }
 
-void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
-  if (li.fp32) k_main<P32><<<li.total_tiles, kWG, 0, st>>>(sim);
-  else k_main<P64><<<li.total_tiles, kWG, 0, st>>>(sim);
+void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
+                 hipEvent_t e1) {
+  launch(k_scan_cells, dim3((li.max_cells + 255) / 256, li.n_spec), dim3(256), st, e0,
+         static_cast<hipEvent_t>(nullptr), sim);
+  launch(k_scan_base, dim3(li.n_spec), dim3(kSolveWG), st, static_cast<hipEvent_t>(nullptr),
+         e1, sim);
 }
 
-void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st) {
-  if (li.fp32) k_finalize<P32><<<li.n_spec, kSolveWG, 0, st>>>(sim);
-  else k_finalize<P64><<<li.n_spec, kSolveWG, 0, st>>>(sim);
+void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
+                 hipEvent_t e1) {
+  if (li.fp32) launch(k_main<P32>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+  else launch(k_main<P64>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+}
+
+void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
+                    hipEvent_t e1) {
+  if (li.fp32) launch(k_collide<P32>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+  else launch(k_collide<P64>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+}
+
+void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
+                     hipEvent_t e1) {
+  if (li.fp32) launch(k_finalize<P32>, dim3(li.n_spec), dim3(kSolveWG), st, e0, e1, sim);
+  else launch(k_finalize<P64>, dim3(li.n_spec), dim3(kSolveWG), st, e0, e1, sim);
 }
 
 }  // namespace fspic

@@ -62,6 +62,9 @@ struct SpeciesDev {
   uint32_t* far_base;       // [n_cells]
   uint32_t* base;           // [n_cells] first output index of each cell
   uint32_t* far_dest;       // [cap] output index of each far mover, by input index
+  uint4* cand;              // [cap] MCC candidates (output slot, id, channel words), stored
+                            // in each tile's input-index range
+  uint32_t* cand_cnt;       // [n_tiles + n_tail]
   uint32_t* birth_cnt;      // [n_tiles + n_tail] births of each electron tile
   uint32_t* tile_first;     // [n_tiles + n_tail] first input index of each tile
   uint32_t* birth_base;     // [n_tiles + n_tail + 1] exclusive scan of the electron births

@@ -1,16 +1,23 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Bar (per result):
+Both sides start from inputs neither of them produced: the Philox load each side draws
+itself from the same seed, or a seeded synthetic state from workloads.synthetic_state
+handed to both.
+
+Bar:
 * integer results -- particle counts, the permutation (id order of the output array),
-  cells, collision / absorption / birth tallies -- bit-exact;
+  cells, collision / absorption / birth tallies -- bit-exact (FP64 path);
 * FP64 path: node weights max|dw| / max w <= 1e-12 per species; positions and velocities
   to 1e-12 (the GPU solves the same tridiagonal system in prefix form, so E differs from
   the Thomas result by rounding only);
-* FP32 cell + offset path, compared with the oracle run in the same layout: push
-  arithmetic is the same FP32 operation sequence, so positions of particles that did not
-  collide agree exactly up to FP32 rounding of the node fields; collided velocities
-  (FP32 kinematics on the GPU) to 1e-5 relative; node weights (FP32 sums of up to a few
-  hundred terms per tile window) to 1e-5 of max w.
+* FP32 cell + offset path, against the oracle run in the same layout.  The kernel
+  accumulates the charge in FP32 (LDS windows), so its field differs from the oracle's
+  (FP64 deposit) by ~1e-6 relative; a particle whose new offset lies that close to a cell
+  edge may land in the neighbouring cell.  So: cells agree except inside a band of width
+  EDGE at a cell edge; positions to 1e-4 cells, velocities to 1e-5 relative; the GPU's
+  output order must be exactly the stable sort, by the GPU's own cells, of the input
+  order (survivors), then the births in parent order; node weights to 1e-5 of max w
+  (FP32 sums of up to a few hundred terms per tile window).
 """
 import numpy as np
 import pytest
@@ -18,6 +25,8 @@ import pytest
 import workloads
 
 pytestmark = pytest.mark.gpu
+
+EDGE = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -30,29 +39,35 @@ def fspic():
     return m
 
 
-def to_oracle(orc, st, fp32):
+def positions(a, fp32):
+    if fp32:
+        return a["cell"].astype(np.float64) + a["off"].astype(np.float64)
+    return np.asarray(a["x"], dtype=np.float64)
+
+
+def velocities(a, fp32):
+    if fp32:
+        return np.stack([a["vxf"], a["vyf"], a["vzf"]]).astype(np.float64)
+    return np.stack([a["vx"], a["vy"], a["vz"]])
+
+
+def oracle_from_state(oracle_mod, wl, st, fp32):
+    """An oracle holding the seeded synthetic state `st`."""
+    caps = [max(int(wl["n_e0"] * 1.5) + 1024, 2 * st[0]["n"]),
+            max(int(wl["n_i0"] * 1.5) + 1024, 2 * st[1]["n"])]
+    orc = oracle_mod.Oracle(wl, fp32_offset=fp32, cap_e=caps[0], cap_i=caps[1])
     for s in (0, 1):
         a = st[s]
-        if fp32:
-            x = a["cell"].astype(np.float64) + a["off"].astype(np.float64)
-            v = [a["vxf"], a["vyf"], a["vzf"]]
-        else:
-            x = a["x"]
-            v = [a["vx"], a["vy"], a["vz"]]
-        orc.set_particles(s, dict(x=x, vx=np.asarray(v[0], np.float64),
-                                  vy=np.asarray(v[1], np.float64),
-                                  vz=np.asarray(v[2], np.float64), id=a["id"]))
+        v = velocities(a, fp32)
+        orc.set_particles(s, dict(x=positions(a, fp32), vx=v[0], vy=v[1], vz=v[2], id=a["id"]))
     orc.set_counters(st["step"], st["next_id"][0], st["next_id"][1])
+    return orc
 
 
-def gpu_arrays(a, fp32):
-    if fp32:
-        x = a["cell"].astype(np.float64) + a["off"].astype(np.float64)
-        v = np.stack([a["vxf"], a["vyf"], a["vzf"]]).astype(np.float64)
-    else:
-        x = a["x"]
-        v = np.stack([a["vx"], a["vy"], a["vz"]])
-    return x, v
+def gpu_from_state(fspic, wl, st, precision, cap_factor=1.5):
+    sim = fspic.Simulation(wl, precision, cap_factor=cap_factor)
+    sim.set_state(st)
+    return sim
 
 
 def tallies_of(diag):
@@ -61,42 +76,87 @@ def tallies_of(diag):
                     births=int(diag.births[s])) for s in (0, 1)}
 
 
-def compare(sim, orc, fp32, label, base=None):
-    """GPU state and tallies (minus `base`, the GPU tallies when the oracle started)
-    against the oracle."""
-    st = sim.get_state()
-    diag = sim.diagnostics()
-    t = orc.tallies()
-    g = tallies_of(diag)
-    if base is not None:
-        for s in (0, 1):
-            g[s]["coll"] = [a - b for a, b in zip(g[s]["coll"], base[s]["coll"])]
-            g[s]["absorbed"] = [a - b for a, b in zip(g[s]["absorbed"], base[s]["absorbed"])]
-            g[s]["births"] -= base[s]["births"]
+def oracle_tallies(t):
+    return {s: dict(coll=[int(t.collisions[s][c]) for c in range(3)],
+                    absorbed=[int(t.absorbed[s][w]) for w in range(2)],
+                    births=int(t.births[s])) for s in (0, 1)}
+
+
+def delta(a, b):
+    return {s: dict(coll=[x - y for x, y in zip(a[s]["coll"], b[s]["coll"])],
+                    absorbed=[x - y for x, y in zip(a[s]["absorbed"], b[s]["absorbed"])],
+                    births=a[s]["births"] - b[s]["births"]) for s in (0, 1)}
+
+
+def compare_fp64(sim, orc, label, gbase=None, obase=None, d=0):
+    """Exact permutation / counts / tallies, 1e-12 on positions, velocities and weights."""
+    st = sim.get_state(d)
+    g = tallies_of(sim.diagnostics(d))
+    o = oracle_tallies(orc.tallies())
+    if gbase is not None:
+        g = delta(g, gbase)
+    if obase is not None:
+        o = delta(o, obase)
+    n_cells = sim.workloads[d]["n_cells"]
     for s in (0, 1):
-        o = orc.particles(s)
+        po = orc.particles(s)
         a = st[s]
         assert a["n"] == orc.count(s), (label, s, "count")
-        assert np.array_equal(a["id"], o["id"]), (label, s, "permutation")
-        x, v = gpu_arrays(a, fp32)
-        vo = np.stack([o["vx"], o["vy"], o["vz"]])
-        if fp32:
-            assert np.array_equal(np.floor(x), np.floor(o["x"])), (label, s, "cells")
-            assert np.max(np.abs(x - o["x"]), initial=0) < 1e-5, (label, s, "x")
-            scale = np.max(np.abs(vo), initial=1e-30)
-            assert np.max(np.abs(v - vo), initial=0) <= 1e-5 * scale, (label, s, "v")
-        else:
-            assert np.max(np.abs(x - o["x"]), initial=0) < 1e-12 * max(1.0, sim.workloads[0]["n_cells"]), (label, s, "x")
-            scale = np.max(np.abs(vo), initial=1e-30)
-            assert np.max(np.abs(v - vo), initial=0) <= 1e-12 * scale, (label, s, "v")
+        assert np.array_equal(a["id"], po["id"]), (label, s, "permutation")
+        x, v = positions(a, False), velocities(a, False)
+        vo = np.stack([po["vx"], po["vy"], po["vz"]])
+        assert np.max(np.abs(x - po["x"]), initial=0) <= 1e-12 * max(1.0, n_cells), (label, s, "x")
+        scale = np.max(np.abs(vo), initial=1e-30)
+        assert np.max(np.abs(v - vo), initial=0) <= 1e-12 * scale, (label, s, "v")
         wo = orc.grid("w_e" if s == 0 else "w_i")
-        wg = a["w"]
-        tol = 1e-5 if fp32 else 1e-12
-        assert np.max(np.abs(wg - wo)) <= tol * max(wo.max(), 1.0), (label, s, "w")
-        assert g[s]["coll"] == [t.collisions[s][c] for c in range(3)], (label, s, "collisions")
-        assert g[s]["absorbed"] == [t.absorbed[s][w] for w in range(2)], (label, s, "absorbed")
-        assert g[s]["births"] == t.births[s], (label, s, "births")
-        assert diag.next_id[s] == t.next_id[s], (label, s, "next_id")
+        assert np.max(np.abs(a["w"] - wo)) <= 1e-12 * max(wo.max(), 1.0), (label, s, "w")
+        assert g[s] == o[s], (label, s, "tallies", g[s], o[s])
+    return st
+
+
+def compare_fp32(sim, orc, st_in, label, gbase=None, obase=None, coll_slack=0, d=0):
+    st = sim.get_state(d)
+    g = tallies_of(sim.diagnostics(d))
+    o = oracle_tallies(orc.tallies())
+    if gbase is not None:
+        g = delta(g, gbase)
+    if obase is not None:
+        o = delta(o, obase)
+    for s in (0, 1):
+        a, po, inp = st[s], orc.particles(s), st_in[s]
+        n = a["n"]
+        assert n == orc.count(s), (label, s, "count")
+        ig, io = np.argsort(a["id"]), np.argsort(po["id"])
+        assert np.array_equal(a["id"][ig], po["id"][io]), (label, s, "id sets")
+        xg, xo = positions(a, True)[ig], po["x"][io]
+        cg, co = a["cell"][ig].astype(np.int64), np.floor(xo).astype(np.int64)
+        fo = xo - co
+        edge = (fo < EDGE) | (fo > 1 - EDGE)
+        bad = (cg != co) & ~edge
+        assert not bad.any(), (label, s, "cells off the edge band", int(bad.sum()))
+        assert np.max(np.abs(xg - xo), initial=0) <= 1e-4, (label, s, "x")
+        vg = velocities(a, True)[:, ig]
+        vo = np.stack([po["vx"], po["vy"], po["vz"]])[:, io]
+        scale = np.max(np.abs(vo), initial=1e-30)
+        assert np.max(np.abs(vg - vo), initial=0) <= 1e-5 * scale, (label, s, "v")
+        # the GPU's order is the stable sort of the input order by the GPU's own cells
+        ns = a["n_sorted"]
+        surv = a["id"][:ns]
+        in_order = inp["id"][np.isin(inp["id"], surv)]
+        by_id = np.argsort(surv)
+        keys = a["cell"][:ns][by_id][np.searchsorted(surv[by_id], in_order)].astype(np.int64)
+        expect = in_order[np.argsort(keys, kind="stable")]
+        assert np.array_equal(expect, surv), (label, s, "stable order")
+        # births: appended in parent order with consecutive new ids
+        born = a["id"][ns:]
+        first = st_in["next_id"][s]
+        assert np.array_equal(born, np.arange(first, first + born.size)), (label, s, "birth ids")
+        wo = orc.grid("w_e" if s == 0 else "w_i")
+        assert np.max(np.abs(a["w"] - wo)) <= 1e-5 * max(wo.max(), 1.0), (label, s, "w")
+        assert g[s]["absorbed"] == o[s]["absorbed"], (label, s, "absorbed")
+        for c in range(3):
+            assert abs(g[s]["coll"][c] - o[s]["coll"][c]) <= coll_slack, (label, s, "collisions")
+        assert abs(g[s]["births"] - o[s]["births"]) <= coll_slack, (label, s, "births")
     return st
 
 
@@ -115,7 +175,8 @@ CASES = [
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
 @pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
 def test_initial_load_matches_oracle(fspic, oracle_mod, name, wl, precision):
-    """Load (Philox tag 1), initial sort by cell, deposit, solve, half-step back-push."""
+    """Load (Philox tag 1, drawn by each side), initial sort by cell, deposit, solve,
+    half-step back-push."""
     fp32 = precision == "fp32_offset"
     print("case", name, precision, flush=True)
     sim = fspic.Simulation(wl, precision)
@@ -127,36 +188,44 @@ def test_initial_load_matches_oracle(fspic, oracle_mod, name, wl, precision):
         a = st[s]
         assert a["n"] == orc.count(s) and a["n_sorted"] == a["n"]
         assert np.array_equal(a["id"], o["id"])
-        x, v = gpu_arrays(a, fp32)
-        assert np.array_equal(x, o["x"])  # no transcendental on the position draw
+        assert np.array_equal(positions(a, fp32), o["x"])  # no transcendental in x
         vo = np.stack([o["vx"], o["vy"], o["vz"]])
         scale = np.max(np.abs(vo), initial=1e-30)
         tol = 1e-6 if fp32 else 1e-14
-        assert np.max(np.abs(v - vo), initial=0) <= tol * scale
+        assert np.max(np.abs(velocities(a, fp32) - vo), initial=0) <= tol * scale
         wo = orc.grid("w_e" if s == 0 else "w_i")
         assert np.max(np.abs(a["w"] - wo)) <= (1e-5 if fp32 else 1e-12) * wo.max()
     sim.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
-@pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
-def test_one_step_from_identical_state(fspic, oracle_mod, name, wl, precision):
+def one_step(fspic, oracle_mod, wl, st, precision, coll_slack=0, label=""):
     fp32 = precision == "fp32_offset"
-    print("case", name, precision, flush=True)
-    sim = fspic.Simulation(wl, precision)
-    sim.step(3)
-    st = sim.get_state()
-    base = tallies_of(sim.diagnostics())
-    orc = oracle_mod.Oracle(wl, fp32_offset=fp32)
-    to_oracle(orc, st, fp32)
+    sim = gpu_from_state(fspic, wl, st, precision)
+    orc = oracle_from_state(oracle_mod, wl, st, fp32)
+    gb = tallies_of(sim.diagnostics())
     sim.step(1)
     orc.step(1)
-    compare(sim, orc, fp32, "%s/%s" % (name, precision), base)
+    if fp32:
+        compare_fp32(sim, orc, st, label, gbase=gb, coll_slack=coll_slack)
+    else:
+        compare_fp64(sim, orc, label, gbase=gb)
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+@pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
+def test_one_step_from_seeded_state(fspic, oracle_mod, name, wl, precision):
+    """One step from the same seeded synthetic state (both species, a births tail of 50
+    particles per species)."""
+    print("case", name, precision, flush=True)
+    st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
+                                   seed=17, vth=(2.0, 0.02), tail=(50, 50))
+    one_step(fspic, oracle_mod, wl, st, precision, label="%s/%s" % (name, precision))
 
 
 @pytest.mark.parametrize("name,wl", CASES, ids=[c[0] for c in CASES])
 def test_fp64_free_running_20_steps(fspic, oracle_mod, name, wl):
+    """Each side loads from the same seed and runs 20 steps on its own."""
     print("case", name, flush=True)
     sim = fspic.Simulation(wl, "fp64")
     orc = oracle_mod.Oracle(wl)
@@ -164,7 +233,7 @@ def test_fp64_free_running_20_steps(fspic, oracle_mod, name, wl):
     for k in range(20):
         sim.step(1)
         orc.step(1)
-        compare(sim, orc, False, "%s step %d" % (name, k))
+        compare_fp64(sim, orc, "%s step %d" % (name, k))
     sim.close()
 
 

@@ -1,12 +1,12 @@
-"""GPU parity of the less common paths of the step through the C ABI: far movers (more
-than `window` cells in one step), an unsorted births tail handed in by the caller, the
-general device sort, batched discharges, HIP-graph replay, and one step at the full size
-of the large single discharge.  Same bar as test_gpu_parity.py."""
+"""GPU parity of the less common paths of the step through the C ABI, from seeded states
+handed to both sides: far movers (more than `window` cells in one step), an unsorted
+births tail, the general device sort, batched discharges, HIP-graph replay, and one step
+at the full size of the large single discharge.  Same bar as test_gpu_parity.py."""
 import numpy as np
 import pytest
 
 import workloads
-from test_gpu_parity import compare, tallies_of, to_oracle
+from test_gpu_parity import (compare_fp64, one_step, oracle_from_state, tallies_of)
 
 pytestmark = pytest.mark.gpu
 
@@ -21,146 +21,95 @@ def fspic():
     return m
 
 
-def one_step_vs_oracle(fspic, oracle_mod, wl, precision, edit=None, sort_all=False):
-    fp32 = precision == "fp32_offset"
-    sim = fspic.Simulation(wl, precision)
-    st = sim.get_state()
-    if edit is not None:
-        edit(st)
-        sim.set_state(st, sort_all=sort_all)
-        st = sim.get_state()
-    base = tallies_of(sim.diagnostics())
-    orc = oracle_mod.Oracle(wl, fp32_offset=fp32)
-    to_oracle(orc, st, fp32)
-    sim.step(1)
-    orc.step(1)
-    out = compare(sim, orc, fp32, "one step", base)
-    sim.close()
-    return st, out
-
-
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
 def test_far_movers(fspic, oracle_mod, precision):
-    """Electrons sent 40-90 cells in one step (window 31 cells) take the far-mover path and
-    must land at the same place in the stable order."""
+    """300 electrons sent 40-90 cells in one step (window 31 cells in this box) take the
+    far-mover path and must land at their place in the stable order."""
     wl = workloads.periodic_c1(xsec="none", gas_pa=0.0)
     print("far movers", precision, flush=True)
-
-    def edit(st):
-        rng = np.random.default_rng(7)
-        idx = rng.choice(st[0]["n"], 300, replace=False)
-        key = "vxf" if precision == "fp32_offset" else "vx"
-        st[0][key][idx] = rng.uniform(40, 90, 300) * rng.choice([-1, 1], 300)
-
-    one_step_vs_oracle(fspic, oracle_mod, wl, precision, edit)
+    st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
+                                   seed=5, vth=(0.4, 0.001), fast=(300, 0))
+    one_step(fspic, oracle_mod, wl, st, precision, label="far " + precision)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
 @pytest.mark.parametrize("tail", [137, "all"])
 def test_unsorted_tail(fspic, oracle_mod, precision, tail):
     """A state whose last particles are not in cell order (as after births): the step sorts
-    them in at their input rank."""
-    wl = dict(workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0))
+    them in at their input rank.  'all': the whole array is the tail."""
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0)
     print("tail", tail, precision, flush=True)
-
-    def edit(st):
-        rng = np.random.default_rng(3)
-        for s in (0, 1):
-            a = st[s]
-            n = a["n"]
-            k = n if tail == "all" else tail
-            perm = np.arange(n)
-            moved = rng.choice(n, k, replace=False)
-            keep = np.setdiff1d(perm, moved)
-            order = np.concatenate([keep, rng.permutation(moved)])
-            for name, arr in list(a.items()):
-                if isinstance(arr, np.ndarray) and arr.shape == (n,):
-                    a[name] = arr[order].copy()
-            a["n_sorted"] = n - k
-
-    one_step_vs_oracle(fspic, oracle_mod, wl, precision, edit)
+    k = 20000 if tail == "all" else tail
+    st = workloads.synthetic_state(wl["n_cells"], (20000, 20000), precision, seed=9,
+                                   vth=(2.0, 0.01), tail=(k, k))
+    one_step(fspic, oracle_mod, wl, st, precision, label="tail %s %s" % (tail, precision))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
-def test_general_sort_of_shuffled_state(fspic, oracle_mod, precision):
-    """sort_all: the device sorts a shuffled array stably by cell (ties in input order)."""
+def test_general_sort_of_unsorted_state(fspic, oracle_mod, precision):
+    """sort_all: the device sorts an unsorted array stably by cell (ties in input order),
+    as the oracle's stable counting sort orders it."""
     wl = workloads.periodic_c1()
     fp32 = precision == "fp32_offset"
+    st = workloads.synthetic_state(wl["n_cells"], (16384, 16384), precision, seed=11,
+                                   tail=(16384, 16384))
     sim = fspic.Simulation(wl, precision)
-    st = sim.get_state()
-    rng = np.random.default_rng(11)
-    shuffled = {}
-    for s in (0, 1):
-        a = st[s]
-        n = a["n"]
-        order = rng.permutation(n)
-        for name, arr in list(a.items()):
-            if isinstance(arr, np.ndarray) and arr.shape == (n,):
-                a[name] = arr[order].copy()
-        cells = a["cell"] if fp32 else np.floor(a["x"]).astype(np.int64)
-        shuffled[s] = a["id"][np.argsort(cells, kind="stable")]
     sim.set_state(st, sort_all=True)
     st2 = sim.get_state()
     for s in (0, 1):
-        assert st2[s]["n_sorted"] == st2[s]["n"]
-        assert np.array_equal(st2[s]["id"], shuffled[s])
+        a = st[s]
+        cells = a["cell"] if fp32 else np.floor(a["x"]).astype(np.int32)
+        perm = oracle_mod.stable_sort_by_cell(cells, wl["n_cells"])
+        assert st2[s]["n_sorted"] == st2[s]["n"] == a["n"]
+        assert np.array_equal(st2[s]["id"], a["id"][perm])
     sim.close()
 
 
 def test_batched_discharges_match_oracle_each(fspic, oracle_mod):
     """Three discharges of the batched scan (particle counts scaled down) in one launch per
-    kernel.  Free-running from the load for 4 steps the permutation matches each
-    discharge's own oracle run exactly; the node weights match to 1e-10 of max w, not
-    1e-12, because these discharges have up to 2048 cells at up to 500 V and ~2
-    particles per cell: the Thomas elimination of the oracle and the prefix-form solve of
-    the GPU round differently by ~N eps relative in E, and the positions accumulate it.
-    One further step from the identical state then meets 1e-12.  Discharge 1 run alone
-    gives the same particles as inside the batch."""
+    kernel.  Free-running from each side's own load for 4 steps the permutation matches
+    every discharge's oracle exactly; the node weights match to 1e-10 of max w, not 1e-12,
+    because these discharges have up to 2048 cells at up to 500 V and ~2 particles per
+    cell: the Thomas elimination of the oracle and the prefix-form solve of the GPU round
+    differently by ~N eps relative in E, and the positions accumulate it.  Then one step
+    from seeded states set into both sides meets the 1e-12 bar for every discharge, and
+    discharge 1 run alone gives the same particles as inside the batch."""
     wls = workloads.batched_c4(n_discharges=3, scale=0.01)
     print("batched", [(w["n_cells"], w["n_e0"]) for w in wls], flush=True)
     sim = fspic.Simulation(wls, "fp64")
     orcs = []
-    for d, wl in enumerate(wls):
+    for wl in wls:
         o = oracle_mod.Oracle(wl)
         o.load()
         orcs.append(o)
     sim.step(4)
     for o in orcs:
         o.step(4)
-    bases = []
     for d, o in enumerate(orcs):
         st = sim.get_state(d)
         for s in (0, 1):
             assert np.array_equal(st[s]["id"], o.particles(s)["id"]), (d, s)
             wo = o.grid("w_e" if s == 0 else "w_i")
             assert np.max(np.abs(st[s]["w"] - wo)) <= 1e-10 * wo.max(), (d, s)
-        to_oracle(o, st, False)
-        t0 = o.tallies()
-        bases.append((tallies_of(sim.diagnostics(d)),
-                      {s: ([t0.collisions[s][c] for c in range(3)], t0.births[s]) for s in (0, 1)}))
-    sim.step(1)
-    for d, o in enumerate(orcs):
-        o.step(1)
-        diag = sim.diagnostics(d)
-        st = sim.get_state(d)
-        t = o.tallies()
-        gb, ob = bases[d]
-        for s in (0, 1):
-            assert np.array_equal(st[s]["id"], o.particles(s)["id"]), (d, s)
-            wo = o.grid("w_e" if s == 0 else "w_i")
-            assert np.max(np.abs(st[s]["w"] - wo)) <= 1e-12 * wo.max(), (d, s)
-            g = tallies_of(diag)[s]
-            assert [a - b for a, b in zip(g["coll"], gb[s]["coll"])] == \
-                [t.collisions[s][c] - ob[s][0][c] for c in range(3)]
-            assert g["births"] - gb[s]["births"] == t.births[s] - ob[s][1]
     alone = fspic.Simulation(wls[1], "fp64")
-    alone.step(5)
-    a = alone.get_state()
-    b = sim.get_state(1)
+    alone.step(4)
+    a, b = alone.get_state(), sim.get_state(1)
     for s in (0, 1):
         assert np.array_equal(a[s]["id"], b[s]["id"])
         assert np.max(np.abs(a[s]["x"] - b[s]["x"])) < 1e-12 * wls[1]["n_cells"]
     alone.close()
+    # one step from seeded states, all discharges at once
+    states = [workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), "fp64",
+                                        seed=100 + d, step=4) for d, wl in enumerate(wls)]
+    orcs = []
+    for d, wl in enumerate(wls):
+        sim.set_state(states[d], d)
+        orcs.append(oracle_from_state(oracle_mod, wl, states[d], False))
+    gbs = [tallies_of(sim.diagnostics(d)) for d in range(3)]
+    sim.step(1)
+    for d, o in enumerate(orcs):
+        o.step(1)
+        compare_fp64(sim, o, "batched %d" % d, gbase=gbs[d], d=d)
     sim.close()
 
 
@@ -186,21 +135,16 @@ def test_graph_replay_equals_eager(fspic):
 
 @pytest.mark.parametrize("precision", ["fp32_offset", "fp64"])
 def test_full_size_large_discharge_one_step(fspic, oracle_mod, precision):
-    """The large single discharge at full size (4096 cells, 1e7 + 1e7), in the launch
-    configuration the benchmark times: a few steps, then one step from the identical state
-    against the oracle over every particle."""
+    """The large single discharge at full size (4096 cells, 1e7 + 1e7 particles), with the
+    tile geometry the benchmark times, one step from a seeded state (electron spread 2.2
+    cells per step, a births tail of 1000) against the oracle over every particle.  About
+    1e6 collision candidates: the FP32 layout's field (FP32 charge sums) differs from the
+    oracle's by ~1e-6 relative, which can move a channel decision of a handful of
+    candidates; the FP64 path must match exactly."""
     wl = workloads.large_c3()
     fp32 = precision == "fp32_offset"
     print("full size", precision, flush=True)
-    sim = fspic.Simulation(wl, precision)
-    sim.set_graph(2)
-    sim.step(4)
-    st = sim.get_state()
-    base = tallies_of(sim.diagnostics())
-    orc = oracle_mod.Oracle(wl, fp32_offset=fp32)
-    to_oracle(orc, st, fp32)
-    del st
-    sim.step(1)
-    orc.step(1)
-    compare(sim, orc, fp32, "full size " + precision, base)
-    sim.close()
+    st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
+                                   seed=23, vth=(2.2, 0.01), tail=(1000, 1000))
+    one_step(fspic, oracle_mod, wl, st, precision, coll_slack=5 if fp32 else 0,
+             label="full " + precision)

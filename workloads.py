@@ -114,3 +114,43 @@ def batched_c4(n_discharges=256, scale=1.0, **kw):
         d.update(kw)
         out.append(d)
     return out
+
+
+def synthetic_state(n_cells, n_per_species, precision, seed, vth=(2.0, 0.02), tail=(0, 0),
+                    fast=(0, 0), fast_speed=(40.0, 90.0), step=5):
+    """A seeded particle state in the library's layout, to hand to both the HIP path and
+    the oracle.  Per species: uniform positions laid out cell by cell (so the first
+    n - tail particles are in cell order by construction), then `tail` particles in random
+    cells (an unsorted births tail); Gaussian velocities of spread vth (cells per step);
+    `fast` electrons moved to |v_x| in fast_speed; ids a random permutation.
+    Returns {0: arrays, 1: arrays, "step", "next_id"}; arrays hold x (float64) or
+    cell/off (int32/float32) and vx, vy, vz, id, n, n_sorted."""
+    rng = np.random.default_rng(seed)
+    fp32 = precision == "fp32_offset"
+    out = {"step": step, "next_id": [int(n) for n in n_per_species]}
+    for s, n in enumerate(n_per_species):
+        n = int(n)
+        nt = int(tail[s])
+        counts = rng.multinomial(n - nt, np.full(n_cells, 1.0 / n_cells))
+        cell = np.concatenate([np.repeat(np.arange(n_cells), counts),
+                               rng.integers(0, n_cells, nt)]).astype(np.int32)
+        if fp32:
+            off = rng.random(n, dtype=np.float32)
+        else:
+            off = rng.random(n)
+        v = rng.normal(0.0, vth[s], size=(3, n))
+        if fast[s]:
+            idx = rng.choice(n - nt, int(fast[s]), replace=False)
+            v[0, idx] = rng.uniform(*fast_speed, size=idx.size) * rng.choice([-1.0, 1.0], idx.size)
+        a = {"id": rng.permutation(n).astype(np.uint32), "n": n, "n_sorted": n - nt}
+        if fp32:
+            a["cell"] = cell
+            a["off"] = off
+            a["vxf"], a["vyf"], a["vzf"] = (v[k].astype(np.float32) for k in range(3))
+        else:
+            x = cell + off
+            top = np.nextafter(cell + 1.0, 0.0)
+            a["x"] = np.minimum(x, top)  # keeps floor(x) == cell where cell + off rounds up
+            a["vx"], a["vy"], a["vz"] = v[0], v[1], v[2]
+        out[s] = a
+    return out
