@@ -3,10 +3,15 @@
 Prints ONE JSON line.  The headline `value` is particle-steps/s of the FP32 cell + offset
 path on the large single discharge (4096 cells, 1e7 electrons + 1e7 ions, 5 Pa Ar-like
 gas, 300 V at 13.56 MHz, sort every step), inputs resident in HBM, K steps replayed from
-a captured HIP graph and timed with HIP events on the library's stream.  The FP64 path on
-the same discharge and the batched 256-discharge scan are reported under "paths"; the
-roofline of the dominant kernel (k_main) and the oracle's CPU speed on a bounded sample
-of the same workload come alongside.
+a captured HIP graph and timed with HIP events on the library's stream.  The same W + K
+steps are then run again from the same seeded load with eager launches, every kernel
+bracketed by HIP events recorded by its own launch: the per-kernel durations of the K
+timed steps give the roofline of the dominant kernel (k_main).  The FP64 path on the same
+discharge and the batched 256-discharge scan are reported under "paths", and the oracle's
+CPU speed on a bounded sample of the same workload comes alongside.
+
+`python bench.py --skip-paths --skip-cpu` runs only the two headline runs; that is the
+command whose rocprofv3 kernel statistics are kept beside the code.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-paths] [--skip-cpu]
 """
@@ -50,15 +55,27 @@ def read_traffic(precision):
     return float(m_b.group(1))
 
 
-def run_path(fs, torch, wls, precision, steps, warmup, graph_k=50, profile_steps=20,
-             tuning=None, cap_factor=1.5):
+def _psteps(sim):
+    return sum(sum(sim.diagnostics(d).particle_steps) for d in range(len(sim.workloads)))
+
+
+def _timed_run(fs, torch, wls, precision, steps, warmup, graph_k, profile, tuning,
+               cap_factor):
+    """One run of warmup + timed steps from a fresh load.  With graph_k the steps replay a
+    captured HIP graph of graph_k steps; with profile they launch eagerly, each kernel
+    bracketed by HIP events (library stream), and the per-kernel durations of the timed
+    steps are returned."""
     sim = fs.Simulation(wls, precision, tuning=tuning, cap_factor=cap_factor)
     stream = sim.stream
-    sim.set_graph(graph_k)
+    if graph_k:
+        sim.set_graph(graph_k)
+    if profile:
+        sim.profile(True)
     sim.step(warmup)
     sim.sync()
-    nd = len(sim.workloads)
-    ps0 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
+    if profile:
+        sim.profile(True)  # drop the warm-up steps from the totals
+    ps0 = _psteps(sim)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -68,34 +85,38 @@ def run_path(fs, torch, wls, precision, steps, warmup, graph_k=50, profile_steps
     e1.record(stream)
     e1.synchronize()
     wall = time.perf_counter() - t0
-    torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     sim.sync()
-    ps1 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
-    psteps = ps1 - ps0
-    # per-kernel durations: eager launches bracketed by HIP events on the same stream
-    sim.profile(True)
-    ps2 = ps1
-    sim.step(profile_steps)
-    sim.sync()
-    prof = sim.profile_read()
-    ps3 = sum(sum(sim.diagnostics(d).particle_steps) for d in range(nd))
-    sim.profile(False)
-    diag = [sim.diagnostics(d) for d in range(nd)]
-    out = {
-        "value": psteps / (ms / 1e3),
-        "ms_per_step": ms / steps,
-        "wall_s": wall,
-        "particle_steps": psteps,
-        "particles_end": int(sum(sum(g.n_particles) for g in diag)),
-        "kernel_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
-        "profile_particle_steps": ps3 - ps2,
-        "profile_steps": profile_steps,
-    }
+    ps1 = _psteps(sim)
+    out = {"value": (ps1 - ps0) / (ms / 1e3), "ms_per_step": ms / steps, "wall_s": wall,
+           "particle_steps": ps1 - ps0,
+           "particles_end": int(sum(sum(sim.diagnostics(d).n_particles)
+                                    for d in range(len(sim.workloads))))}
+    if profile:
+        prof = sim.profile_read()
+        out["kernel_ms"] = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+        out["kernel_launches"] = {k: v[1] for k, v in prof.items()}
+        sim.profile(False)
     sim.close()
     del sim
     torch.cuda.empty_cache()
     return out
+
+
+def run_path(fs, torch, wls, precision, steps, warmup, graph_k=50, tuning=None,
+             cap_factor=1.5):
+    """The same trajectory twice from the same seeded load: replayed from a HIP graph
+    (the throughput `value`), then eagerly with per-kernel events over the same timed
+    steps (the kernel durations).  The runs are deterministic, so both time the same
+    work."""
+    g = _timed_run(fs, torch, wls, precision, steps, warmup, graph_k, False, tuning,
+                   cap_factor)
+    e = _timed_run(fs, torch, wls, precision, steps, warmup, 0, True, tuning, cap_factor)
+    return {"value": g["value"], "ms_per_step": g["ms_per_step"], "wall_s": g["wall_s"],
+            "particle_steps": g["particle_steps"], "particles_end": g["particles_end"],
+            "eager_value": e["value"], "eager_ms_per_step": e["ms_per_step"],
+            "eager_particle_steps": e["particle_steps"], "kernel_ms": e["kernel_ms"],
+            "steps": steps}
 
 
 def cpu_baseline(wl, steps):
@@ -125,9 +146,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--path-steps", type=int, default=400)
     ap.add_argument("--batched-scale", type=float, default=1.0)
-    ap.add_argument("--mode", choices=["bench", "profile", "copy"], default="bench",
-                    help="profile: only the headline path, for rocprofv3; copy: a plain "
-                         "device copy of known size that calibrates the HBM byte counters")
+    ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
+                    help="copy: a plain device copy of known size that calibrates the HBM "
+                         "byte counters of rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a discharge (or a batch of "
@@ -152,11 +173,6 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
         return
     large = workloads.large_c3()
-    if args.mode == "profile":
-        r = run_path(fs, torch, large, "fp32_offset", args.steps, args.warmup, profile_steps=5)
-        print(json.dumps({"mode": "profile", "value": r["value"], "steps": args.steps,
-                          "particle_steps": r["particle_steps"], "kernel_ms": r["kernel_ms"]}))
-        return
     print("bench: FP32 cell+offset, large discharge, %d steps" % args.steps, file=sys.stderr,
           flush=True)
     head = run_path(fs, torch, large, "fp32_offset", args.steps, args.warmup)
@@ -165,7 +181,8 @@ def main():
         print("bench: FP64, large discharge", file=sys.stderr, flush=True)
         r64 = run_path(fs, torch, large, "fp64", args.path_steps, args.warmup)
         paths["fp64"] = {"value": r64["value"], "ms_per_step": r64["ms_per_step"],
-                         "steps": args.path_steps, "kernel_ms": r64["kernel_ms"]}
+                         "eager_value": r64["eager_value"], "steps": args.path_steps,
+                         "kernel_ms": r64["kernel_ms"]}
         print("bench: batched scan", file=sys.stderr, flush=True)
         batch = workloads.batched_c4(scale=args.batched_scale)
         # the hottest discharges of the scan (55-95 Pa, 400-490 V, < 2.5 cm) more than
@@ -173,11 +190,12 @@ def main():
         rb = run_path(fs, torch, batch, "fp32_offset", args.path_steps, args.warmup,
                       cap_factor=4.0)
         paths["batched"] = {"value": rb["value"], "ms_per_step": rb["ms_per_step"],
-                            "steps": args.path_steps, "discharges": len(batch),
+                            "eager_value": rb["eager_value"], "steps": args.path_steps,
+                            "discharges": len(batch),
                             "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"]}
     # roofline of the dominant kernel (k_main), FP32 path
     kmain_ms = head["kernel_ms"]["main"]
-    ps_per_launch = head["profile_particle_steps"] / head["profile_steps"]
+    ps_per_launch = head["eager_particle_steps"] / head["steps"]
     alg_bytes = 2 * REC_BYTES["fp32_offset"] * ps_per_launch
     achieved = alg_bytes / (kmain_ms / 1e3) / 1e9
     traffic = read_traffic("fp32_offset")
@@ -209,6 +227,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "paths": dict({"fp32_offset": {"value": head["value"], "ms_per_step": head["ms_per_step"],
+                                       "eager_value": head["eager_value"],
+                                       "particles_end": head["particles_end"],
                                        "kernel_ms": head["kernel_ms"]}}, **paths),
     }
     print(json.dumps(line))

@@ -172,8 +172,15 @@ int pic_diagnostics(pic_sim* sim, int discharge, pic_diag* out); /* syncs */
 int pic_get_state(pic_sim* sim, int discharge, pic_state* st);        /* syncs */
 int pic_set_state(pic_sim* sim, int discharge, const pic_state* st);  /* syncs */
 
-/* Per-phase kernel timing (eager launches bracketed by HIP events on the sim's stream).
-   Phases: 0 combine, 1 solve, 2 hist, 3 scan, 4 main, 5 collide, 6 finalize. */
+/* Per-phase kernel timing.  While enabled, steps launch eagerly (no graph) and every
+   kernel is launched with a start and a stop HIP event on the sim's stream, recorded by
+   the launch itself around the kernel's execution.  The events of up to 32 steps are in
+   flight before they are read, so profiling does not idle the GPU between steps.
+   pic_profile(sim, 1|0) turns it on or off and resets the totals; pic_profile_read
+   waits for the recorded steps and returns, per phase, the summed milliseconds and the
+   number of steps.  Phases: 0 combine, 1 solve, 2 hist, 3 scan (two kernels: from the
+   start of the first to the end of the second), 4 main, 5 collide, 6 finalize.
+   Errors: PIC_ERR_STATE (null sim), PIC_ERR_ARG (null outputs), PIC_ERR_DEVICE. */
 int pic_profile(pic_sim* sim, int enable);
 int pic_profile_read(pic_sim* sim, double* ms_total, uint64_t* launches, int n_phases);
 

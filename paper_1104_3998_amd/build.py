@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "fspic")
 LIB = os.path.join(HERE, "libfspic.so")
-SOURCES = ["api.hip", "kernels_step.hip", "kernels_setup.hip", "physics_host.cpp"]
+SOURCES = ["api.cpp", "kernels_step.hip", "kernels_setup.hip", "physics_host.cpp"]
 ARCH = os.environ.get("FSPIC_ARCH", "gfx950")
 
 
@@ -38,7 +38,9 @@ def flags():
 
 def _compile(src):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    # .cpp files hold host code only (no kernels): no device pass
+    host_only = ["--offload-host-only"] if src.endswith(".cpp") else []
+    cmd = [hipcc()] + flags() + host_only + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

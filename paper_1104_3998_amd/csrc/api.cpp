@@ -1,4 +1,4 @@
-// api.hip -- the C ABI of libfspic (include/fspic.h): configuration checks, the carve-up
+// api.cpp -- the C ABI of libfspic (include/fspic.h): configuration checks, the carve-up
 // of the caller's workspace, the launch sequence of a step (eager or replayed from a
 // captured HIP graph), state upload/download and diagnostics.
 #include <hip/hip_runtime.h>
@@ -18,6 +18,7 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr int kPhases = 7;
+constexpr int kRing = 32;  // steps whose phase events are in flight before they are read
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -50,6 +51,26 @@ struct Plan {
   size_t bytes = 0;
 };
 
+// Workgroup -> tile table of the particle kernels.  Workgroups are handed to the 8 XCDs
+// in turn (workgroup b to XCD b mod 8), and each XCD has its own L2; the table gives
+// each XCD one contiguous run of the tile list, so neighbouring tiles -- whose outputs
+// share cache lines at the cell boundaries -- are written through the same L2.  The
+// (small) tail tiles go first so that they start early.
+std::vector<int2> xcd_order(const std::vector<int2>& tail, const std::vector<int2>& cells) {
+  constexpr int kXcds = 8;
+  std::vector<int2> list(tail);
+  list.insert(list.end(), cells.begin(), cells.end());
+  const size_t n = list.size();
+  std::vector<int2> table(n);
+  size_t start = 0;
+  for (int x = 0; x < kXcds; ++x) {
+    const size_t count = n > static_cast<size_t>(x) ? (n - x + kXcds - 1) / kXcds : 0;
+    for (size_t m = 0; m < count; ++m) table[m * kXcds + x] = list[start + m];
+    start += count;
+  }
+  return table;
+}
+
 int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* why) {
   if (!cfgs || n < 1) {
     *why = "need at least one configuration";
@@ -78,6 +99,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   pl->sp.assign(2 * n, SpeciesDev{});
   pl->ds.assign(n, DischargeDev{});
   pl->tile_table.clear();
+  std::vector<int2> cell_tiles, tail_tiles;
   int max_nodes = 0, max_cap = 0, max_cells = 0;
   for (int d = 0; d < n; ++d) {
     const pic_config& c = cfgs[d];
@@ -126,16 +148,19 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.n_nodes = nn;
       S.cap = cap;
       S.far_cap = c.far_capacity > 0 ? c.far_capacity : std::max<uint32_t>(65536u, cap / 8u);
+      // particle and candidate arrays hold one element past the capacity: a sink that
+      // lanes without a record to store write to, so that stores are not branched over
+      const size_t cap1 = static_cast<size_t>(cap) + 1;
       for (int b = 0; b < 2; ++b) {
         if (fp32) {
-          S.fld[b][F32_CELL] = cv.take<int>(cap);
-          S.fld[b][F32_OFF] = cv.take<float>(cap);
+          S.fld[b][F32_CELL] = cv.take<int>(cap1);
+          S.fld[b][F32_OFF] = cv.take<float>(cap1);
         } else {
-          S.fld[b][F64_X] = cv.take<double>(cap);
+          S.fld[b][F64_X] = cv.take<double>(cap1);
           S.fld[b][1] = nullptr;
         }
-        for (int f = F_VX; f <= F_VZ; ++f) S.fld[b][f] = cv.take<char>(rs * cap);
-        S.fld[b][F_ID] = cv.take<uint32_t>(cap);
+        for (int f = F_VX; f <= F_VZ; ++f) S.fld[b][f] = cv.take<char>(rs * cap1);
+        S.fld[b][F_ID] = cv.take<uint32_t>(cap1);
       }
       if (s == 0) {
         for (int b = 0; b < 2; ++b) {
@@ -154,8 +179,10 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.n_sorted = cv.take<uint32_t>(2);
       S.next_id = cv.take<uint32_t>(1);
       S.cell_start = cv.take<uint32_t>(2 * (N + 1));
-      S.hist = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * tc.W);
-      S.tilerel = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * tc.W);
+      S.hist = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * kWaves * tc.W);
+      S.tilerel = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * kWaves * tc.W);
+      S.thist = cv.take<uint32_t>(static_cast<size_t>(tc.n_tail) * kWaves * N);
+      S.trel = cv.take<uint32_t>(static_cast<size_t>(tc.n_tail) * kWaves * N);
       S.partial = cv.take<char>(rs * static_cast<size_t>(tc.n_tiles) * (tc.W + 1));
       S.far_w = cv.take<double>(nn);
       S.far_count = cv.take<uint32_t>(1);
@@ -167,8 +194,9 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.base = cv.take<uint32_t>(N);
       S.far_dest = cv.take<uint32_t>(cap);
       const int ntt = tc.n_tiles + tc.n_tail;
-      S.cand = cv.take<uint4>(cap);
-      S.cand_cnt = cv.take<uint32_t>(ntt);
+      S.cand = cv.take<uint4>(cap1);
+      for (int f = 0; f < 4; ++f) S.cand_f[f] = cv.take<char>(rs * cap1);
+      S.cand_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
       S.birth_cnt = cv.take<uint32_t>(ntt);
       S.tile_first = cv.take<uint32_t>(ntt);
       // births of both species are ranked over the electron tiles
@@ -198,13 +226,11 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.lang_mode = static_cast<int>(c.langmuir_mode);
       S.vth = k.vth[s];
       S.lang_amp = c.langmuir_amp_cells;
-      S.tile_base = static_cast<int>(pl->tile_table.size());
-      for (int t = 0; t < tc.n_tiles; ++t) pl->tile_table.push_back(make_int2(2 * d + s, t));
-      S.tail_base = static_cast<int>(pl->tile_table.size());
-      for (int j = 0; j < tc.n_tail; ++j)
-        pl->tile_table.push_back(make_int2(2 * d + s, tc.n_tiles + j));
+      for (int t = 0; t < tc.n_tiles; ++t) cell_tiles.push_back(make_int2(2 * d + s, t));
+      for (int j = 0; j < tc.n_tail; ++j) tail_tiles.push_back(make_int2(2 * d + s, tc.n_tiles + j));
     }
   }
+  pl->tile_table = xcd_order(tail_tiles, cell_tiles);
   const int n_gtiles = 256;
   for (int i = 0; i < 2 * n; ++i)
     pl->sp[i].gsort_hist = cv.take<uint32_t>(static_cast<size_t>(n_gtiles) * pl->sp[i].n_cells);
@@ -249,7 +275,8 @@ struct pic_sim {
   hipStream_t cap_stream = nullptr;
   // profiling
   bool prof = false;
-  hipEvent_t ev[2 * kPhases] = {};
+  hipEvent_t ev[kRing][2 * kPhases] = {};
+  int ring_used = 0;  // steps recorded in the ring and not yet read
   double ms[kPhases] = {};
   uint64_t cnt[kPhases] = {};
 };
@@ -312,6 +339,23 @@ extern "C" int pic_derive(const pic_config* cfg, pic_derived* out) {
   return derive(*cfg, out);
 }
 
+// Reads the phase events of the steps recorded so far (waits for the last of them) and
+// adds their durations to the per-phase totals.  Events are read in batches so that a
+// profiled run keeps the GPU as busy as an unprofiled one.
+static int drain_profile(pic_sim* sim) {
+  if (sim->ring_used == 0) return PIC_OK;
+  HIPCHECK(sim, hipEventSynchronize(sim->ev[sim->ring_used - 1][2 * kPhases - 1]));
+  for (int k = 0; k < sim->ring_used; ++k)
+    for (int p = 0; p < kPhases; ++p) {
+      float ms = 0.0f;
+      HIPCHECK(sim, hipEventElapsedTime(&ms, sim->ev[k][2 * p], sim->ev[k][2 * p + 1]));
+      sim->ms[p] += ms;
+      sim->cnt[p] += 1;
+    }
+  sim->ring_used = 0;
+  return PIC_OK;
+}
+
 static int step_once(pic_sim* sim, hipStream_t st) {
   const LaunchInfo& li = sim->pl.li;
   const SimDev* d = sim->pl.d_sim;
@@ -325,7 +369,11 @@ static int step_once(pic_sim* sim, hipStream_t st) {
     launch_finalize(li, d, st);
     return launch_check(sim, "step launch");
   }
-  hipEvent_t* ev = sim->ev;
+  if (sim->ring_used == kRing) {
+    const int rc = drain_profile(sim);
+    if (rc != PIC_OK) return rc;
+  }
+  hipEvent_t* ev = sim->ev[sim->ring_used];
   launch_combine(li, d, st, ev[0], ev[1]);
   launch_solve(li, d, 0, st, ev[2], ev[3]);
   launch_hist(li, d, st, ev[4], ev[5]);
@@ -333,16 +381,8 @@ static int step_once(pic_sim* sim, hipStream_t st) {
   launch_main(li, d, st, ev[8], ev[9]);
   launch_collide(li, d, st, ev[10], ev[11]);
   launch_finalize(li, d, st, ev[12], ev[13]);
-  int rc = launch_check(sim, "step launch");
-  if (rc != PIC_OK) return rc;
-  HIPCHECK(sim, hipEventSynchronize(ev[2 * kPhases - 1]));
-  for (int p = 0; p < kPhases; ++p) {
-    float ms = 0.0f;
-    HIPCHECK(sim, hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
-    sim->ms[p] += ms;
-    sim->cnt[p] += 1;
-  }
-  return PIC_OK;
+  sim->ring_used += 1;
+  return launch_check(sim, "step launch");
 }
 
 extern "C" int pic_init(const pic_config* cfgs, int n, void* d_workspace, size_t bytes,
@@ -775,8 +815,13 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
 
 extern "C" int pic_profile(pic_sim* sim, int enable) {
   if (!sim) return PIC_ERR_STATE;
-  if (enable && !sim->ev[0])
-    for (int i = 0; i < 2 * kPhases; ++i) HIPCHECK(sim, hipEventCreate(&sim->ev[i]));
+  if (enable && !sim->ev[0][0])
+    for (int k = 0; k < kRing; ++k)
+      for (int i = 0; i < 2 * kPhases; ++i) HIPCHECK(sim, hipEventCreate(&sim->ev[k][i]));
+  if (sim->prof) {
+    const int rc = drain_profile(sim);
+    if (rc != PIC_OK) return rc;
+  }
   sim->prof = enable != 0;
   for (int i = 0; i < kPhases; ++i) {
     sim->ms[i] = 0.0;
@@ -787,6 +832,8 @@ extern "C" int pic_profile(pic_sim* sim, int enable) {
 
 extern "C" int pic_profile_read(pic_sim* sim, double* ms, uint64_t* launches, int n) {
   if (!sim || !ms || !launches) return PIC_ERR_ARG;
+  const int rc = drain_profile(sim);
+  if (rc != PIC_OK) return rc;
   for (int i = 0; i < n && i < kPhases; ++i) {
     ms[i] = sim->ms[i];
     launches[i] = sim->cnt[i];
@@ -799,8 +846,9 @@ extern "C" void pic_free(pic_sim* sim) {
   if (sim->stream) hipStreamSynchronize(sim->stream);
   if (sim->exec) hipGraphExecDestroy(sim->exec);
   if (sim->cap_stream) hipStreamDestroy(sim->cap_stream);
-  for (int i = 0; i < 2 * kPhases; ++i)
-    if (sim->ev[i]) hipEventDestroy(sim->ev[i]);
+  for (int k = 0; k < kRing; ++k)
+    for (int i = 0; i < 2 * kPhases; ++i)
+      if (sim->ev[k][i]) hipEventDestroy(sim->ev[k][i]);
   delete sim;
 }
 

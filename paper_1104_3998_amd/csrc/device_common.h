@@ -239,6 +239,43 @@ __device__ __forceinline__ void for_covering(const SpeciesDev& s, int j, int spa
   }
 }
 
+// The tiles of for_covering as (at most) two index ranges [a0, b0], [a1, b1], visited in
+// that order (an empty range has b < a), and the slot of cell / node j in tile t's window.
+__device__ __forceinline__ void covering_ranges(const SpeciesDev& s, int j, int span, int a[2],
+                                                int b[2]) {
+  const int C = s.C, D = s.D, n = s.n_tiles;
+  const int thi = floordiv(j + D, C);
+  const int tlo = floordiv(j + D - span, C) + 1;
+  a[1] = 0;
+  b[1] = -1;
+  if (!s.periodic) {
+    a[0] = tlo < 0 ? 0 : tlo;
+    b[0] = thi > n - 1 ? n - 1 : thi;
+  } else if (tlo < 0) {
+    a[0] = 0;
+    b[0] = thi;
+    a[1] = tlo + n;
+    b[1] = n - 1;
+  } else if (thi > n - 1) {
+    a[0] = 0;
+    b[0] = thi - n;
+    a[1] = tlo;
+    b[1] = n - 1;
+  } else {
+    a[0] = tlo;
+    b[0] = thi;
+  }
+}
+
+__device__ __forceinline__ int covering_slot(const SpeciesDev& s, int j, int t) {
+  int k = j - t * s.C + s.D;
+  if (s.periodic) {
+    k %= s.n_cells;
+    if (k < 0) k += s.n_cells;
+  }
+  return k;
+}
+
 // slot of cell d in the window of tile t, or -1 if outside [0, W)
 __device__ __forceinline__ int window_slot(const SpeciesDev& s, int t, int d) {
   int k = d - (t * s.C - s.D);
@@ -252,6 +289,11 @@ __device__ __forceinline__ int window_slot(const SpeciesDev& s, int t, int d) {
 // ------------------------------------------------------------------------------------
 // Wave-level helpers.
 // ------------------------------------------------------------------------------------
+// Index of this thread's wave in the workgroup, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+}
+
 __device__ __forceinline__ unsigned long long lanes_below() {
   const int lane = threadIdx.x & 63;
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -316,8 +358,8 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T& total) {
 }
 
 // In-place exclusive scan of a[0..n) by one workgroup; returns the total.
-template <class T>
-__device__ T array_exclusive_scan(T* a, int n, T* lds) {
+template <class T, class Ptr>
+__device__ T array_exclusive_scan(Ptr a, int n, T* lds) {
   __threadfence();
   __syncthreads();
   const int per = (n + blockDim.x - 1) / blockDim.x;

@@ -24,33 +24,33 @@ struct Rec<S64> {
   using real = double;
 };
 
-__device__ __forceinline__ int cell_of32(void* const* f, uint32_t i) {
-  return static_cast<const int*>(f[F32_CELL])[i];
+__device__ __forceinline__ int cell_of32(void GM* const* f, uint32_t i) {
+  return static_cast<const int GM*>(f[F32_CELL])[i];
 }
-__device__ __forceinline__ int cell_of64(void* const* f, uint32_t i) {
-  return static_cast<int>(floor(static_cast<const double*>(f[F64_X])[i]));
+__device__ __forceinline__ int cell_of64(void GM* const* f, uint32_t i) {
+  return static_cast<int>(floor(static_cast<const double GM*>(f[F64_X])[i]));
 }
 
 template <class P>
-__device__ __forceinline__ int cell_of(void* const* f, uint32_t i) {
+__device__ __forceinline__ int cell_of(void GM* const* f, uint32_t i) {
   if constexpr (std::is_same<P, S32>::value) return cell_of32(f, i);
   else return cell_of64(f, i);
 }
 
 template <class P>
-__device__ __forceinline__ void copy_record(void* const* src, uint32_t i, void* const* dst,
+__device__ __forceinline__ void copy_record(void GM* const* src, uint32_t i, void GM* const* dst,
                                             uint32_t j) {
   if constexpr (std::is_same<P, S32>::value) {
-    static_cast<int*>(dst[F32_CELL])[j] = static_cast<const int*>(src[F32_CELL])[i];
-    static_cast<float*>(dst[F32_OFF])[j] = static_cast<const float*>(src[F32_OFF])[i];
+    static_cast<int GM*>(dst[F32_CELL])[j] = static_cast<const int GM*>(src[F32_CELL])[i];
+    static_cast<float GM*>(dst[F32_OFF])[j] = static_cast<const float GM*>(src[F32_OFF])[i];
     for (int f = F_VX; f <= F_VZ; ++f)
-      static_cast<float*>(dst[f])[j] = static_cast<const float*>(src[f])[i];
+      static_cast<float GM*>(dst[f])[j] = static_cast<const float GM*>(src[f])[i];
   } else {
-    static_cast<double*>(dst[F64_X])[j] = static_cast<const double*>(src[F64_X])[i];
+    static_cast<double GM*>(dst[F64_X])[j] = static_cast<const double GM*>(src[F64_X])[i];
     for (int f = F_VX; f <= F_VZ; ++f)
-      static_cast<double*>(dst[f])[j] = static_cast<const double*>(src[f])[i];
+      static_cast<double GM*>(dst[f])[j] = static_cast<const double GM*>(src[f])[i];
   }
-  static_cast<uint32_t*>(dst[F_ID])[j] = static_cast<const uint32_t*>(src[F_ID])[i];
+  static_cast<uint32_t GM*>(dst[F_ID])[j] = static_cast<const uint32_t GM*>(src[F_ID])[i];
 }
 
 // ------------------------------------------------------------------------------------
@@ -62,7 +62,7 @@ __device__ __forceinline__ void copy_record(void* const* src, uint32_t i, void* 
 template <class P>
 __global__ __launch_bounds__(256) void k_load(const SimDev* __restrict__ simp, int dst) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.y];
+  const SpeciesDev s = sim.sp[blockIdx.y];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s.n_init) return;
   const int N = s.n_cells;
@@ -87,17 +87,17 @@ __global__ __launch_bounds__(256) void k_load(const SimDev* __restrict__ simp, i
       for (int it = 0; it < 4 && x >= dn; ++it) x -= dn;
     }
   }
-  void* const* f = s.fld[dst];
+  void GM* const* f = s.fld[dst];
   if constexpr (std::is_same<P, S32>::value) {
     const double c = floor(x);
-    static_cast<int*>(f[F32_CELL])[i] = static_cast<int>(c);
-    static_cast<float*>(f[F32_OFF])[i] = __double2float_rz(x - c);
-    for (int a = 0; a < 3; ++a) static_cast<float*>(f[F_VX + a])[i] = static_cast<float>(v[a]);
+    static_cast<int GM*>(f[F32_CELL])[i] = static_cast<int>(c);
+    static_cast<float GM*>(f[F32_OFF])[i] = __double2float_rz(x - c);
+    for (int a = 0; a < 3; ++a) static_cast<float GM*>(f[F_VX + a])[i] = static_cast<float>(v[a]);
   } else {
-    static_cast<double*>(f[F64_X])[i] = x;
-    for (int a = 0; a < 3; ++a) static_cast<double*>(f[F_VX + a])[i] = v[a];
+    static_cast<double GM*>(f[F64_X])[i] = x;
+    for (int a = 0; a < 3; ++a) static_cast<double GM*>(f[F_VX + a])[i] = v[a];
   }
-  static_cast<uint32_t*>(f[F_ID])[i] = i;
+  static_cast<uint32_t GM*>(f[F_ID])[i] = i;
 }
 
 // ------------------------------------------------------------------------------------
@@ -112,14 +112,14 @@ __global__ __launch_bounds__(64) void k_gsort_hist(const SimDev* __restrict__ si
                                                    int n_gtiles) {
   extern __shared__ uint32_t hist[];
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.y];
+  const SpeciesDev s = sim.sp[blockIdx.y];
   const int N = s.n_cells;
   const uint32_t n = s.n_total[src];
   const uint32_t per = (n + n_gtiles - 1) / n_gtiles;
   const uint32_t lo = min(n, blockIdx.x * per), hi = min(n, lo + per);
   for (int c = threadIdx.x; c < N; c += blockDim.x) hist[c] = 0u;
   __syncthreads();
-  void* const* f = s.fld[src];
+  void GM* const* f = s.fld[src];
   for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     int c = cell_of<P>(f, i);
     c = c < 0 ? 0 : (c >= N ? N - 1 : c);
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(64) void k_gsort_hist(const SimDev* __restrict__ si
 __global__ __launch_bounds__(kSolveWG) void k_gsort_scan(const SimDev* __restrict__ simp,
                                                          int src, int dst, int n_gtiles) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.x];
+  const SpeciesDev s = sim.sp[blockIdx.x];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
   const int N = s.n_cells;
   const uint32_t n = s.n_total[src];
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(64) void k_gsort_scatter(const SimDev* __restrict__
                                                       int dst, int n_gtiles) {
   extern __shared__ uint32_t run[];
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.y];
+  const SpeciesDev s = sim.sp[blockIdx.y];
   const int N = s.n_cells;
   const uint32_t n = s.n_total[src];
   const uint32_t per = (n + n_gtiles - 1) / n_gtiles;
@@ -172,8 +172,8 @@ __global__ __launch_bounds__(64) void k_gsort_scatter(const SimDev* __restrict__
   __syncthreads();
   const int lane = threadIdx.x;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  void* const* fs = s.fld[src];
-  void* const* fd = s.fld[dst];
+  void GM* const* fs = s.fld[src];
+  void GM* const* fd = s.fld[dst];
   for (uint32_t b = lo; b < hi; b += 64) {
     const uint32_t i = b + lane;
     bool active = i < hi;
@@ -207,12 +207,12 @@ template <class P>
 __global__ __launch_bounds__(256) void k_cell_start(const SimDev* __restrict__ simp, int spec,
                                                     int buf) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[spec];
+  const SpeciesDev s = sim.sp[spec];
   const int N = s.n_cells;
   const uint32_t ns = s.n_sorted[buf];
   uint32_t* cs = s.cell_start + buf * (N + 1);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  void* const* f = s.fld[buf];
+  void GM* const* f = s.fld[buf];
   if (ns == 0) {
     for (int c = i; c <= N; c += gridDim.x * blockDim.x) cs[c] = 0u;
     return;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict_
   using real = typename Rec<P>::real;
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
-  const SpeciesDev& s = sim.sp[tt.x];
+  const SpeciesDev s = sim.sp[tt.x];
   if (ds_filter >= 0 && s.ds != ds_filter) return;
   const int p = static_cast<int>(*sim.step & 1ull);
   const int t = tt.y;
@@ -257,17 +257,17 @@ __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict_
   }
   for (int k = threadIdx.x; k <= W; k += blockDim.x) dep[k] = real(0);
   __syncthreads();
-  void* const* f = s.fld[p];
+  void GM* const* f = s.fld[p];
   for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     int c;
     double fr;
     real frr;
     if constexpr (std::is_same<P, S32>::value) {
-      c = static_cast<const int*>(f[F32_CELL])[i];
-      frr = static_cast<const float*>(f[F32_OFF])[i];
+      c = static_cast<const int GM*>(f[F32_CELL])[i];
+      frr = static_cast<const float GM*>(f[F32_OFF])[i];
       fr = static_cast<double>(frr);
     } else {
-      const double x = static_cast<const double*>(f[F64_X])[i];
+      const double x = static_cast<const double GM*>(f[F64_X])[i];
       const double cc = floor(x);
       c = static_cast<int>(cc);
       fr = x - cc;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict_
   }
   __syncthreads();
   if (!tail) {
-    real* part = static_cast<real*>(s.partial) + static_cast<size_t>(t) * (W + 1);
+    real* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(t) * (W + 1);
     for (int k = threadIdx.x; k <= W; k += blockDim.x) part[k] = dep[k];
   }
 }
@@ -296,35 +296,35 @@ __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict_
 template <class P>
 __global__ __launch_bounds__(256) void k_halfstep(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.y];
-  const DischargeDev& dd = sim.ds[s.ds];
+  const SpeciesDev s = sim.sp[blockIdx.y];
+  const DischargeDev dd = sim.ds[s.ds];
   const int p = static_cast<int>(*sim.step & 1ull);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s.n_total[p]) return;
-  void* const* f = s.fld[p];
+  void GM* const* f = s.fld[p];
   const int N = s.n_cells;
   if constexpr (std::is_same<P, S32>::value) {
-    const int c = static_cast<const int*>(f[F32_CELL])[i];
+    const int c = static_cast<const int GM*>(f[F32_CELL])[i];
     if (c < 0 || c >= N) return;
     const int cn = (s.periodic && c + 1 == N) ? 0 : c + 1;
-    const float fr = static_cast<const float*>(f[F32_OFF])[i];
+    const float fr = static_cast<const float GM*>(f[F32_OFF])[i];
     const float t = 1.0f - fr;
     const float a = t * dd.E32[c];
     const float b = fr * dd.E32[cn];
     const float ep = a + b;
     const float hk = 0.5f * s.kappa_f;
     const float dv = hk * ep;
-    float* vx = static_cast<float*>(f[F_VX]);
+    float* vx = static_cast<float GM*>(f[F_VX]);
     vx[i] = vx[i] - dv;
   } else {
-    const double x = static_cast<const double*>(f[F64_X])[i];
+    const double x = static_cast<const double GM*>(f[F64_X])[i];
     if (!(x >= 0.0 && x < static_cast<double>(N))) return;
     const double cc = floor(x);
     const int c = static_cast<int>(cc);
     const int cn = (s.periodic && c + 1 == N) ? 0 : c + 1;
     const double fr = x - cc;
     const double ep = (1.0 - fr) * dd.E64[c] + fr * dd.E64[cn];
-    double* vx = static_cast<double*>(f[F_VX]);
+    double* vx = static_cast<double GM*>(f[F_VX]);
     vx[i] = vx[i] - 0.5 * s.kappa * ep;
   }
 }

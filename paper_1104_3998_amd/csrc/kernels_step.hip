@@ -27,6 +27,20 @@ namespace fspic {
 struct P32 {};
 struct P64 {};
 
+// The six field pointers of one particle array (or staging set), read once per launch from
+// the descriptor so that they live in scalar registers for the whole particle loop.
+struct RecPtr {
+  void GM* f[6];
+  __device__ __forceinline__ void GM* operator[](int k) const { return f[k]; }
+};
+
+__device__ __forceinline__ RecPtr rec_of(void GM* const CM* f) {
+  RecPtr r;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.f[k] = f[k];
+  return r;
+}
+
 template <class P>
 struct Part;
 
@@ -36,13 +50,13 @@ struct Part<P32> {
   int cell;
   float off, vx, vy, vz;
   uint32_t id;
-  __device__ __forceinline__ void load(void* const* f, uint32_t i) {
-    cell = static_cast<const int*>(f[F32_CELL])[i];
-    off = static_cast<const float*>(f[F32_OFF])[i];
-    vx = static_cast<const float*>(f[F_VX])[i];
-    vy = static_cast<const float*>(f[F_VY])[i];
-    vz = static_cast<const float*>(f[F_VZ])[i];
-    id = static_cast<const uint32_t*>(f[F_ID])[i];
+  __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
+    cell = static_cast<const int GM*>(f[F32_CELL])[i];
+    off = static_cast<const float GM*>(f[F32_OFF])[i];
+    vx = static_cast<const float GM*>(f[F_VX])[i];
+    vy = static_cast<const float GM*>(f[F_VY])[i];
+    vz = static_cast<const float GM*>(f[F_VZ])[i];
+    id = static_cast<const uint32_t GM*>(f[F_ID])[i];
   }
 };
 
@@ -51,12 +65,12 @@ struct Part<P64> {
   using real = double;
   double x, vx, vy, vz;
   uint32_t id;
-  __device__ __forceinline__ void load(void* const* f, uint32_t i) {
-    x = static_cast<const double*>(f[F64_X])[i];
-    vx = static_cast<const double*>(f[F_VX])[i];
-    vy = static_cast<const double*>(f[F_VY])[i];
-    vz = static_cast<const double*>(f[F_VZ])[i];
-    id = static_cast<const uint32_t*>(f[F_ID])[i];
+  __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
+    x = static_cast<const double GM*>(f[F64_X])[i];
+    vx = static_cast<const double GM*>(f[F_VX])[i];
+    vy = static_cast<const double GM*>(f[F_VY])[i];
+    vz = static_cast<const double GM*>(f[F_VZ])[i];
+    id = static_cast<const uint32_t GM*>(f[F_ID])[i];
   }
 };
 
@@ -64,22 +78,22 @@ struct Part<P64> {
 // unless kWithId is false (birth staging keeps no id: k_finalize numbers the births when it
 // appends them, and the staging arrays have no id field).
 template <class P, bool kWithId = true>
-__device__ __forceinline__ void store_record(void* const* f, uint32_t i, int d,
+__device__ __forceinline__ void store_record(const RecPtr& f, uint32_t i, int d,
                                              typename Part<P>::real pos,
                                              typename Part<P>::real vx,
                                              typename Part<P>::real vy,
                                              typename Part<P>::real vz, uint32_t id) {
   if constexpr (std::is_same<P, P32>::value) {
-    static_cast<int*>(f[F32_CELL])[i] = d;
-    static_cast<float*>(f[F32_OFF])[i] = pos;
+    static_cast<int GM*>(f[F32_CELL])[i] = d;
+    static_cast<float GM*>(f[F32_OFF])[i] = pos;
   } else {
-    static_cast<double*>(f[F64_X])[i] = pos;
+    static_cast<double GM*>(f[F64_X])[i] = pos;
   }
   using real = typename Part<P>::real;
-  static_cast<real*>(f[F_VX])[i] = vx;
-  static_cast<real*>(f[F_VY])[i] = vy;
-  static_cast<real*>(f[F_VZ])[i] = vz;
-  if constexpr (kWithId) static_cast<uint32_t*>(f[F_ID])[i] = id;
+  static_cast<real GM*>(f[F_VX])[i] = vx;
+  static_cast<real GM*>(f[F_VY])[i] = vy;
+  static_cast<real GM*>(f[F_VZ])[i] = vz;
+  if constexpr (kWithId) static_cast<uint32_t GM*>(f[F_ID])[i] = id;
 }
 
 struct TileRange {
@@ -94,7 +108,7 @@ __device__ __forceinline__ TileRange tile_range(const SpeciesDev& s, int t, int 
   if (!r.tail) {
     r.c0 = t * s.C;
     const int c1 = min(r.c0 + s.C, s.n_cells);
-    const uint32_t* cs = s.cell_start + p * (s.n_cells + 1);
+    const uint32_t GM* cs = s.cell_start + p * (s.n_cells + 1);
     r.lo = cs[r.c0];
     r.hi = cs[c1];
   } else {
@@ -110,10 +124,87 @@ __device__ __forceinline__ TileRange tile_range(const SpeciesDev& s, int t, int 
   return r;
 }
 
+// A tile's index range [lo, hi) is cut into kWaves contiguous pieces (multiples of 64
+// particles except the last); wave w takes piece w, so the waves of a tile need no
+// synchronisation and each (tile, wave) is its own unit of the stable order.
+struct WaveRange {
+  uint32_t lo, hi;
+};
+
+__device__ __forceinline__ WaveRange wave_range(const TileRange& r, int w) {
+  const uint32_t n = r.hi - r.lo;
+  const uint32_t q = (n + kWaves * 64 - 1) / (kWaves * 64) * 64;
+  WaveRange wr;
+  // wave-uniform: keeps the particle loop a scalar loop
+  wr.lo = __builtin_amdgcn_readfirstlane(min(r.hi, r.lo + static_cast<uint32_t>(w) * q));
+  wr.hi = __builtin_amdgcn_readfirstlane(min(r.hi, wr.lo + q));
+  return wr;
+}
+
+// Streams a wave's range [lo, hi) through `body` in chunks of 64 consecutive particles
+// (lane l takes lo + 64 j + l), U chunks per pass, with the loads of the next pass issued
+// before the current pass is worked on.  `body(item, index, valid)` runs on all 64 lanes.
+// The loads are not conditional (lanes past the end re-read the last element), so a
+// pass always issues the same memory instructions; with the bodies' stores also
+// unconditional, the compiler can wait for exactly the loads of the pass it needs instead
+// of for every outstanding access.
+template <class T, int U, class Load, class Body>
+__device__ __forceinline__ void stream_range(uint32_t lo, uint32_t hi, Load&& load,
+                                             Body&& body) {
+  if (lo >= hi) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t last = hi - 1u;
+  T nxt[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) load(nxt[u], min(lo + static_cast<uint32_t>(u) * 64u + lane, last));
+  for (uint32_t b = lo; b < hi; b += U * 64u) {
+    T cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      load(nxt[u], min(b + static_cast<uint32_t>(U + u) * 64u + lane, last));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = b + static_cast<uint32_t>(u) * 64u + lane;
+      body(cur[u], i, i < hi);
+    }
+  }
+}
+
+// The fields the push reads (the sort pre-pass loads only these).
+template <class P>
+struct PushIn;
+
+template <>
+struct PushIn<P32> {
+  int cell;
+  float off, vx;
+  __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
+    cell = static_cast<const int GM*>(f[F32_CELL])[i];
+    off = static_cast<const float GM*>(f[F32_OFF])[i];
+    vx = static_cast<const float GM*>(f[F_VX])[i];
+  }
+};
+
+template <>
+struct PushIn<P64> {
+  double x, vx;
+  __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
+    x = static_cast<const double GM*>(f[F64_X])[i];
+    vx = static_cast<const double GM*>(f[F_VX])[i];
+  }
+};
+
+__device__ __forceinline__ int key_bits(int n) {
+  int b = 0;
+  while ((1 << b) < n) ++b;
+  return b;
+}
 // Loads the field of the tile's nodes [c0, c0 + C] into LDS (node index wrapped when
 // periodic).  Tail tiles read the global array instead.
 template <class real>
-__device__ __forceinline__ void load_field_window(const SpeciesDev& s, const real* E,
+__device__ __forceinline__ void load_field_window(const SpeciesDev& s, const real GM* E,
                                                   const TileRange& r, real* Elds) {
   if (r.tail) return;
   for (int k = threadIdx.x; k <= s.C; k += blockDim.x) {
@@ -124,21 +215,29 @@ __device__ __forceinline__ void load_field_window(const SpeciesDev& s, const rea
   }
 }
 
-template <class real>
-__device__ __forceinline__ real field_at(const SpeciesDev& s, const real* E, const real* Elds,
+// Field at a node.  A cell tile's particles sit in its own cells, so their nodes are in
+// the tile's LDS window (the clamp only guards a corrupt state); tail particles read the
+// global array.  kTail is a compile-time flag so that the two reads stay an LDS read and
+// a global read (a run-time choice between the two pointers would make a flat load).
+template <class real, bool kTail>
+__device__ __forceinline__ real field_at(const SpeciesDev& s, const real GM* E, const real* Elds,
                                          const TileRange& r, int node) {
-  int k = node - r.c0;
-  if (!r.tail && k >= 0 && k <= s.C) return Elds[k];
-  if (s.periodic && node >= s.n_cells) node -= s.n_cells;
-  return E[node];
+  if constexpr (!kTail) {
+    int k = node - r.c0;
+    k = k < 0 ? 0 : (k > s.C ? s.C : k);
+    return Elds[k];
+  } else {
+    if (s.periodic && node >= s.n_cells) node -= s.n_cells;
+    return E[node];
+  }
 }
 
 // Push one particle: returns status (0 kept, 1/2 wall, 3 invalid), the destination cell
 // d, the new position word (offset or x) and the new v_x.
-template <class P>
+template <class P, bool kTail, class Q>
 __device__ __forceinline__ int push_particle(const SpeciesDev& s, const DischargeDev& dd,
                                              const typename Part<P>::real* Elds,
-                                             const TileRange& r, const Part<P>& q, int& d,
+                                             const TileRange& r, const Q& q, int& d,
                                              typename Part<P>::real& pos,
                                              typename Part<P>::real& vxn) {
   if constexpr (std::is_same<P, P32>::value) {
@@ -149,8 +248,8 @@ __device__ __forceinline__ int push_particle(const SpeciesDev& s, const Discharg
       vxn = q.vx;
       return 3;
     }
-    const float e0 = field_at<float>(s, dd.E32, Elds, r, c);
-    const float e1 = field_at<float>(s, dd.E32, Elds, r, c + 1);
+    const float e0 = field_at<float, kTail>(s, dd.E32, Elds, r, c);
+    const float e1 = field_at<float, kTail>(s, dd.E32, Elds, r, c + 1);
     return push32(c, q.off, q.vx, e0, e1, s.kappa_f, s.n_cells, s.periodic, d, pos, vxn);
   } else {
     if (!(q.x >= 0.0 && q.x < static_cast<double>(s.n_cells))) {
@@ -160,8 +259,8 @@ __device__ __forceinline__ int push_particle(const SpeciesDev& s, const Discharg
       return 3;
     }
     const int c = static_cast<int>(floor(q.x));
-    const double e0 = field_at<double>(s, dd.E64, Elds, r, c);
-    const double e1 = field_at<double>(s, dd.E64, Elds, r, c + 1);
+    const double e0 = field_at<double, kTail>(s, dd.E64, Elds, r, c);
+    const double e1 = field_at<double, kTail>(s, dd.E64, Elds, r, c + 1);
     return push64(q.x, q.vx, e0, e1, s.kappa, s.n_cells, s.periodic, pos, vxn, d);
   }
 }
@@ -174,23 +273,30 @@ __device__ __forceinline__ bool diag_step(const DischargeDev& dd, unsigned long 
 }
 
 // ====================================================================================
-// k_combine: w_s[j] = sum over the tiles whose deposit window holds node j (fixed tile
-// order) + the far / birth deposits.  Grid: (node blocks, species).
+// k_combine: w_s[j] = sum over the tiles whose deposit window holds node j + the far /
+// birth deposits.  One wave per node; the sum runs in a fixed reduction tree, so it is
+// reproducible.  Grid: (node blocks, species).
 // ====================================================================================
 template <class real>
 __global__ __launch_bounds__(256) void k_combine(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.y];
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const SpeciesDev s = sim.sp[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * kWaves + wave_id();  // one wave per node
   if (j >= s.n_nodes) return;
-  const real* part = static_cast<const real*>(s.partial);
+  const real GM* part = static_cast<const real GM*>(s.partial);
   const int span = s.W + 1;
+  int a[2], b[2];
+  covering_ranges(s, j, span, a, b);
+  const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
+  const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
   double sum = 0.0;
-  for_covering(s, j, span, [&](int t, int k) {
-    sum += static_cast<double>(part[static_cast<size_t>(t) * span + k]);
-  });
-  sum += s.far_w[j];
-  sim.ds[s.ds].w[s.sp][j] = sum;
+  for (int u = lane; u < n0 + n1; u += 64) {
+    const int t = u < n0 ? a[0] + u : a[1] + (u - n0);
+    sum += static_cast<double>(part[static_cast<size_t>(t) * span + covering_slot(s, j, t)]);
+  }
+  sum = wave_sum(sum);
+  if (lane == 0) sim.ds[s.ds].w[s.sp][j] = sum + s.far_w[j];
 }
 
 // ====================================================================================
@@ -205,14 +311,14 @@ __global__ __launch_bounds__(256) void k_combine(const SimDev* __restrict__ simp
 __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ simp,
                                                     int init_mode) {
   const SimDev& sim = *simp;
-  const DischargeDev& dd = sim.ds[blockIdx.x];
+  const DischargeDev dd = sim.ds[blockIdx.x];
   __shared__ double lds_d[kSolveWG / 64 + 1];
   const unsigned long long step = init_mode ? 0ull : *sim.step;
   const int N = dd.n_cells;
   const int nn = dd.n_nodes;
-  const double* we = dd.w[0];
-  const double* wi = dd.w[1];
-  double* phi = dd.phi;  // holds R_j, then Phi
+  const double GM* we = dd.w[0];
+  const double GM* wi = dd.w[1];
+  double GM* phi = dd.phi;  // holds R_j, then Phi
   double* E = dd.E64;    // holds s_j, then E
   const int per = (N + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per;
@@ -262,7 +368,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
   __syncthreads();
   if (!dd.periodic && threadIdx.x == 0) phi[N] = 0.0;
   // E from the slopes (E[j] holds s_j for j < N)
-  double* tmp = dd.scratch;
+  double GM* tmp = dd.scratch;
   for (int j = threadIdx.x; j < N; j += blockDim.x) tmp[j] = E[j];
   __syncthreads();
   for (int j = threadIdx.x; j < nn; j += blockDim.x) {
@@ -292,7 +398,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
   if (!init_mode && threadIdx.x == 0 && diag_step(dd, step)) *dd.eedf_samples += 1ull;
   // per-step far-mover state of both species starts empty
   for (int sp = 0; sp < 2; ++sp) {
-    const SpeciesDev& s = sim.sp[dd.spec0 + sp];
+    const SpeciesDev s = sim.sp[dd.spec0 + sp];
     for (int j = threadIdx.x; j < nn; j += blockDim.x) s.far_w[j] = 0.0;
     for (int c = threadIdx.x; c < N; c += blockDim.x) s.far_cell_cnt[c] = 0u;
     if (threadIdx.x == 0) *s.far_count = 0u;
@@ -300,100 +406,172 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
 }
 
 // ====================================================================================
-// k_hist: post-push cell histogram of each tile over its window (sort pre-pass).
-// Each wave keeps its own LDS histogram; lanes with the same slot are grouped with
-// ballots and one leader adds the group's count, so there is no atomic traffic on the
-// crowded slots.  Particles leaving the window (and the unsorted births tail) go to the
-// far list.  Two particles per thread per pass keep more loads in flight.
+// k_hist: post-push cell histogram (sort pre-pass).  Each wave counts its own piece of
+// the tile into its own LDS row over the tile's window: lanes with the same slot are
+// grouped with ballots and one leader adds the group's count.  Particles that leave the
+// window go to the far list.  A tail tile (the unsorted births at the end of the array)
+// has no window: each of its waves counts into its own global row over all cells.
 // ====================================================================================
+template <class P>
+struct HistU;
+template <>
+struct HistU<P32> {
+  static constexpr int value = 4;
+};
+template <>
+struct HistU<P64> {
+  static constexpr int value = 2;
+};
+
 template <class P>
 __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
-  const SpeciesDev& s = sim.sp[tt.x];
-  const DischargeDev& dd = sim.ds[s.ds];
+  const SpeciesDev s = sim.sp[tt.x];
+  const DischargeDev dd = sim.ds[s.ds];
   const int p = static_cast<int>(*sim.step & 1ull);
   const TileRange r = tile_range(s, tt.y, p);
   __shared__ real Elds[kMaxCellsPerTile + 1];
   __shared__ uint32_t h[kWaves][kMaxWindow];
-  const int tid = threadIdx.x, wv = tid >> 6;
+  __shared__ uint32_t hq[kWaves][64][2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const unsigned long long lt = lanes_below();
-  const real* E = std::is_same<P, P32>::value ? reinterpret_cast<const real*>(dd.E32)
-                                               : reinterpret_cast<const real*>(dd.E64);
+  const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
+                                                  : reinterpret_cast<const real GM*>(dd.E64);
   load_field_window<real>(s, E, r, Elds);
   const int W = s.W;
   for (int k = tid; k < kWaves * W; k += kWG) h[k / W][k % W] = 0u;
-  int nbits = 0;
-  while ((1 << nbits) < W) ++nbits;
+  const int nbits = key_bits(W);
   __syncthreads();
-  void* const* in = s.fld[p];
-  for (uint32_t b = r.lo; b < r.hi; b += 2 * kWG) {
-    Part<P> q[2];
-    bool valid[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const uint32_t i = b + u * kWG + tid;
-      valid[u] = i < r.hi;
-      if (valid[u]) q[u].load(in, i);
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const uint32_t i = b + u * kWG + tid;
-      int st = 4, d = 0;
-      real pos, vxn;
-      if (valid[u]) st = push_particle<P>(s, dd, Elds, r, q[u], d, pos, vxn);
-      const int k = (st == 0 && !r.tail) ? window_slot(s, tt.y, d) : -1;
-      const bool near = k >= 0;
-      const unsigned long long m = match_key(k, near, nbits);
-      if (near && __popcll(m & lt) == 0) h[wv][k] += static_cast<uint32_t>(__popcll(m));
-      if (st == 0 && !near) {
-        const uint32_t e = atomicAdd(s.far_count, 1u);
+  const WaveRange wr = wave_range(r, wv);
+  const RecPtr in = rec_of(sim.sp[tt.x].fld[p]);
+  auto load = [&](PushIn<P>& q, uint32_t i) { q.load(in, i); };
+  if (!r.tail) {
+    // far movers wait in a per-wave LDS queue and are appended to the far list after the
+    // loop (a returning atomic inside the loop would make it wait for the next loads)
+    uint32_t qn = 0;  // wave-uniform
+    auto flush = [&]() {
+      uint32_t e0 = 0u;
+      if (lane == 0) e0 = atomicAdd(s.far_count, qn);
+      e0 = __shfl(e0, 0, 64);
+      const uint32_t j = static_cast<uint32_t>(lane);  // the queue holds at most 64
+      if (j < qn) {
+        const uint32_t e = e0 + j;
+        const uint32_t d = hq[wv][j][0];
         if (e < s.far_cap) {
-          s.far_list[e] = make_uint4(static_cast<uint32_t>(d), i, static_cast<uint32_t>(tt.y), 0u);
+          s.far_list[e] = make_uint4(d, hq[wv][j][1], static_cast<uint32_t>(tt.y), 0u);
           atomicAdd(&s.far_cell_cnt[d], 1u);
         }
       }
-    }
+      qn = 0;
+    };
+    stream_range<PushIn<P>, HistU<P>::value>(
+        wr.lo, wr.hi, load, [&](const PushIn<P>& q, uint32_t i, bool valid) {
+          int st = 4, d = 0;
+          real pos, vxn;
+          if (valid) st = push_particle<P, false>(s, dd, Elds, r, q, d, pos, vxn);
+          const int k = st == 0 ? window_slot(s, tt.y, d) : -1;
+          const bool near = k >= 0;
+          const unsigned long long m = match_key(k, near, nbits);
+          if (near && __popcll(m & lt) == 0) h[wv][k] += static_cast<uint32_t>(__popcll(m));
+          const bool far = st == 0 && !near;
+          const unsigned long long fm = __ballot(far);
+          if (fm) {
+            if (qn + static_cast<uint32_t>(__popcll(fm)) > 64u) flush();
+            if (far) {
+              const uint32_t j = qn + static_cast<uint32_t>(__popcll(fm & lt));
+              hq[wv][j][0] = static_cast<uint32_t>(d);
+              hq[wv][j][1] = i;
+            }
+            qn += static_cast<uint32_t>(__popcll(fm));
+          }
+        });
+    if (qn) flush();
+    uint32_t GM* row = s.hist + (static_cast<size_t>(tt.y) * kWaves + wv) * W;
+    for (int k = lane; k < W; k += 64) row[k] = h[wv][k];
+  } else {
+    uint32_t GM* row = s.thist +
+                    static_cast<size_t>((tt.y - s.n_tiles) * kWaves + wv) * s.n_cells;
+    stream_range<PushIn<P>, HistU<P>::value>(
+        wr.lo, wr.hi, load, [&](const PushIn<P>& q, uint32_t i, bool valid) {
+          int st = 4, d = 0;
+          real pos, vxn;
+          if (valid) st = push_particle<P, true>(s, dd, Elds, r, q, d, pos, vxn);
+          if (st == 0) atomicAdd(&row[d], 1u);
+        });
   }
-  __syncthreads();
-  if (!r.tail)
-    for (int k = tid; k < W; k += kWG)
-      s.hist[static_cast<size_t>(tt.y) * W + k] = h[0][k] + h[1][k] + h[2][k] + h[3][k];
 }
 
 // ====================================================================================
 // Output offsets.  Output order = stable sort of the survivors by cell (ties in input
-// order).  For cell c:
-//   count(c) = sum of the covering tiles' histogram entries + far movers into c,
+// order).  The units of that order are, in input order: the (tile, wave) pieces of the
+// cell tiles, then the (tail tile, wave) pieces of the tail.  For cell c:
+//   count(c) = histogram entries of the covering (tile, wave) units + far movers into c
+//              + tail-row entries,
 //   base(c)  = exclusive scan of count;
-//   a tile t's particles in c start at base(c) + (far movers into c from tiles < t)
-//              + (histogram entries of the covering tiles < t);
+//   a cell-tile unit (t, w) starts at base(c) + (far movers into c from tiles < t)
+//              + (entries of the covering units before (t, w));
 //   a far mover from tile u starts at base(c) + (its rank by index among the far movers
-//              into c) + (histogram entries of the covering tiles < u).
-// k_scan_cells does the per-cell part across the whole chip; k_scan_base (one workgroup
-// per discharge and species) scans over cells and places the far movers.
+//              into c) + (entries of the covering units of tiles < u);
+//   tail row j starts after all of the cell tiles' particles and far movers in c and the
+//              tail rows before j.
+// k_scan_cells does the per-cell part across the whole chip (and clears the tail rows
+// for the next step); k_scan_base (one workgroup per discharge and species) scans over
+// cells and places the far movers.
 // ====================================================================================
 constexpr uint32_t kMaxFarGroup = 8192;
 
+// One wave per cell: lane u takes the u-th covering (tile, wave) unit of the cell (in
+// the order of the stable sort), and a wave scan gives every unit its offset.
 __global__ __launch_bounds__(256) void k_scan_cells(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.y];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= s.n_cells) return;
+  const SpeciesDev s = sim.sp[blockIdx.y];
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * kWaves + wave_id();
+  const int N = s.n_cells;
+  if (c >= N) return;
   const int W = s.W;
+  int a[2], b[2];
+  covering_ranges(s, c, W, a, b);
+  const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
+  const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
+  const int units = (n0 + n1) * kWaves;
   uint32_t run = 0;
-  for_covering(s, c, W, [&](int t, int k) {
-    const size_t o = static_cast<size_t>(t) * W + k;
-    s.tilerel[o] = run;
-    run += s.hist[o];
-  });
-  s.base[c] = run + s.far_cell_cnt[c];
+  for (int u0 = 0; u0 < units; u0 += 64) {
+    const int u = u0 + lane;
+    uint32_t v = 0u;
+    size_t o = 0;
+    if (u < units) {
+      const int ti = u / kWaves, w = u - ti * kWaves;
+      const int t = ti < n0 ? a[0] + ti : a[1] + (ti - n0);
+      o = (static_cast<size_t>(t) * kWaves + w) * W + covering_slot(s, c, t);
+      v = s.hist[o];
+    }
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (u < units) s.tilerel[o] = run + inc - v;
+    run += __shfl(inc, 63, 64);
+  }
+  run += s.far_cell_cnt[c];
+  const int rows = s.n_tail * kWaves;
+  for (int j0 = 0; j0 < rows; j0 += 64) {
+    const int jj = j0 + lane;
+    uint32_t v = 0u;
+    const size_t o = static_cast<size_t>(jj) * N + c;
+    if (jj < rows) v = s.thist[o];
+    const uint32_t inc = wave_inclusive_scan(v);
+    if (jj < rows) {
+      s.trel[o] = run + inc - v;
+      s.thist[o] = 0u;
+    }
+    run += __shfl(inc, 63, 64);
+  }
+  if (lane == 0) s.base[c] = run;
 }
 
 __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.x];
+  const SpeciesDev s = sim.sp[blockIdx.x];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
   const int q = static_cast<int>((*sim.step + 1ull) & 1ull);
   const int N = s.n_cells, W = s.W;
@@ -418,7 +596,7 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
     }
     __threadfence();
     __syncthreads();
-    // tiles' offsets in cells that receive far movers from lower tiles
+    // the cell-tile units' offsets in cells that receive far movers from lower tiles
     for (int c = threadIdx.x; c < N; c += blockDim.x) {
       const uint32_t g = s.far_cell_cnt[c];
       if (g == 0u) continue;
@@ -430,7 +608,9 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
       for_covering(s, c, W, [&](int t, int k) {
         uint32_t fb = 0;
         for (uint32_t m = 0; m < g; ++m) fb += s.far_grouped[gb + m].z < static_cast<uint32_t>(t);
-        s.tilerel[static_cast<size_t>(t) * W + k] += fb;
+        if (fb == 0u) return;
+        for (int w = 0; w < kWaves; ++w)
+          s.tilerel[(static_cast<size_t>(t) * kWaves + w) * W + k] += fb;
       });
     }
     for (uint32_t e = threadIdx.x; e < F; e += blockDim.x) {
@@ -444,37 +624,47 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
       for (uint32_t m = 0; m < g; ++m) rank += s.far_grouped[gb + m].y < v.y;
       uint32_t nb = 0;
       for_covering(s, c, W, [&](int t, int k) {
-        if (static_cast<uint32_t>(t) < v.z) nb += s.hist[static_cast<size_t>(t) * W + k];
+        if (static_cast<uint32_t>(t) < v.z)
+          for (int w = 0; w < kWaves; ++w)
+            nb += s.hist[(static_cast<size_t>(t) * kWaves + w) * W + k];
       });
       s.far_dest[v.y] = s.base[c] + rank + nb;
     }
   }
-  uint32_t* cs = s.cell_start + q * (N + 1);
+  uint32_t GM* cs = s.cell_start + q * (N + 1);
   for (int c = threadIdx.x; c < N; c += blockDim.x) cs[c] = s.base[c];
   if (threadIdx.x == 0) {
     cs[N] = n_surv;
     s.n_sorted[q] = n_surv;
   }
 }
-
 // ====================================================================================
-// k_main: the fused particle pass of one tile.
+// k_main: the fused particle pass of one tile.  Each wave streams its piece of the tile:
+// push + gather (Sec. 3.6), walls and EEDF (Sec. 2), the stable scatter of the survivors
+// (its own running offset per window slot, so the output order is the one the histograms
+// promised), the null-collision test (candidates listed with their post-push state),
+// and the linear deposit into its own LDS window (Sec. 3.4).  Tail tiles rank their
+// particles per cell against their global tail rows.
 // ====================================================================================
 constexpr int kReduceSlots = 4;     // up to this many distinct slots a wave reduces in
                                     // registers; more, and it adds with LDS atomics
 constexpr uint32_t kNoDest = 0xFFFFFFFFu;
+constexpr int kFarQ = 64;           // per-wave queue of far movers (one chunk always fits)
 
 template <class P>
 struct MainShared {
   using real = typename Part<P>::real;
   real Elds[kMaxCellsPerTile + 1];
-  uint32_t off[kMaxWindow];
-  uint32_t wcnt[kWaves][kMaxWindow];
-  real dep[kWaves][kMaxWindow + 1];
-  uint32_t cq[kWaves + 1];   // per-wave candidate append position; [kWaves] = tile total
+  uint32_t off[kWaves][kMaxWindow];  // next output index of each (wave, window slot)
+  real dep[kWaves][kMaxWindow + 1];  // per-wave deposit windows
   uint32_t eedf[kMaxEedfBins + 1];
   uint32_t abs_cnt[2];
   double abs_e[2];
+  uint32_t err;                      // error bits found by the tile
+  // far movers deferred to the end of each wave's loop: index, cell, position word,
+  // vx, vy, vz (FP32 bits), id, candidate entry; FP64 keeps the reals in fqd
+  uint32_t fq[kWaves][kFarQ][8];
+  double fqd[kWaves][std::is_same<real, double>::value ? kFarQ : 1][4];
 };
 
 // One collision test of a candidate (Sec. 3.8): returns the channel (0 null).
@@ -618,65 +808,77 @@ __device__ __forceinline__ void deposit_weights(typename Part<P>::real pos,
 }
 
 template <class P>
+struct MainU;
+template <>
+struct MainU<P32> {
+  static constexpr int value = 2;
+};
+template <>
+struct MainU<P64> {
+  static constexpr int value = 1;
+};
+
+template <class P>
 __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
-  const SpeciesDev& s = sim.sp[tt.x];
-  const DischargeDev& dd = sim.ds[s.ds];
+  const SpeciesDev s = sim.sp[tt.x];
+  const DischargeDev dd = sim.ds[s.ds];
   const unsigned long long step = *sim.step;
   const uint32_t step32 = static_cast<uint32_t>(step);
   const int p = static_cast<int>(step & 1ull), pq = p ^ 1;
   const TileRange r = tile_range(s, tt.y, p);
   const int tile = tt.y;
   __shared__ MainShared<P> sh;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const unsigned long long lt = lanes_below();
   const bool eedf_on = s.sp == 0 && diag_step(dd, step);
   const bool far_ok = (*sim.error & kErrFarOverflow) == 0u;
   const uint32_t n_out = s.n_sorted[pq];
-  const real* E = std::is_same<P, P32>::value ? reinterpret_cast<const real*>(dd.E32)
-                                               : reinterpret_cast<const real*>(dd.E64);
+  const uint32_t sink = s.cap;  // the extra element past the capacity of every array
+  const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
+                                                  : reinterpret_cast<const real GM*>(dd.E64);
   load_field_window<real>(s, E, r, sh.Elds);
   const int W = s.W;
-  for (int k = tid; k < W; k += kWG) {
-    int c = tile * s.C - s.D + k;
-    if (s.periodic) {
-      c %= s.n_cells;
-      if (c < 0) c += s.n_cells;
+  if (!r.tail) {
+    for (int k = tid; k < kWaves * W; k += kWG) {
+      const int w = k / W, kk = k - w * W;
+      int c = tile * s.C - s.D + kk;
+      if (s.periodic) {
+        c %= s.n_cells;
+        if (c < 0) c += s.n_cells;
+      }
+      sh.off[w][kk] = (c >= 0 && c < s.n_cells)
+                          ? s.base[c] + s.tilerel[(static_cast<size_t>(tile) * kWaves + w) * W + kk]
+                          : 0u;
     }
-    sh.off[k] = (!r.tail && c >= 0 && c < s.n_cells)
-                    ? s.base[c] + s.tilerel[static_cast<size_t>(tile) * W + k]
-                    : 0u;
   }
   for (int k = tid; k < kWaves * (W + 1); k += kWG) sh.dep[k / (W + 1)][k % (W + 1)] = real(0);
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG) sh.eedf[k] = 0u;
   if (tid == 0) {
-    sh.cq[kWaves] = 0u;
     sh.abs_cnt[0] = sh.abs_cnt[1] = 0u;
     sh.abs_e[0] = sh.abs_e[1] = 0.0;
+    sh.err = 0u;
   }
-  int nbits = 0;
-  while ((1 << nbits) < W) ++nbits;
   __syncthreads();
-  void* const* in = s.fld[p];
-  void* const* out = s.fld[pq];
-  Part<P> nxt;
-  bool nxt_ok = r.lo + tid < r.hi;
-  if (nxt_ok) nxt.load(in, r.lo + tid);
-  for (uint32_t base_i = r.lo; base_i < r.hi; base_i += kWG) {
-    const uint32_t i = base_i + tid;
-    const bool valid = nxt_ok;
-    const Part<P> q = nxt;
-    {  // issue the next chunk's loads before working on this one
-      const uint32_t ni = i + kWG;
-      nxt_ok = ni < r.hi;
-      if (nxt_ok) nxt.load(in, ni);
-    }
-    int st = 4, d = 0;
-    real pos = real(0), vxn = real(0);
-    if (valid) st = push_particle<P>(s, dd, sh.Elds, r, q, d, pos, vxn);
+  const WaveRange wr = wave_range(r, wv);
+  const RecPtr in = rec_of(sim.sp[tt.x].fld[p]);
+  const RecPtr out = rec_of(sim.sp[tt.x].fld[pq]);
+  real GM* const cpos = static_cast<real GM*>(s.cand_f[0]);
+  real GM* const cvx = static_cast<real GM*>(s.cand_f[1]);
+  real GM* const cvy = static_cast<real GM*>(s.cand_f[2]);
+  real GM* const cvz = static_cast<real GM*>(s.cand_f[3]);
+  uint32_t n_cand = 0;  // candidates of this wave so far (wave-uniform)
+  auto load = [&](Part<P>& q, uint32_t i) { q.load(in, i); };
+
+  // Push, walls, EEDF and the null-collision test: common to both kinds of tile.
+  auto push_and_test = [&](auto tail_tag, const Part<P>& q, bool valid, int& d, real& pos,
+                           real& vxn, bool& cand) {
+    constexpr bool kTail = decltype(tail_tag)::value;
+    int st = 4;
+    if (valid) st = push_particle<P, kTail>(s, dd, sh.Elds, r, q, d, pos, vxn);
     if (valid && (eedf_on || st == 1 || st == 2)) {
       const double v2 = static_cast<double>(vxn) * static_cast<double>(vxn) +
                         static_cast<double>(q.vy) * static_cast<double>(q.vy) +
@@ -691,94 +893,184 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
         atomicAdd(&sh.abs_e[st - 1], s.energy_c * v2);
       }
     }
-    if (st == 3) atomicOr(sim.error, kErrState);
-    bool cand = false;
-    uint4 b0 = make_uint4(0u, 0u, 0u, 0u);
-    if (st == 0 && s.t0 != 0u) {
-      b0 = philox(q.id, step32, 0u, 0u, s.key0, s.key1);
-      cand = b0.x < s.t0;
-    }
-    const int k = (st == 0 && !r.tail) ? window_slot(s, tile, d) : -1;
-    const bool near = k >= 0;
-    const unsigned long long m = match_key(k, near, nbits);
-    const int rank = __popcll(m & lt);
-    for (int kk = lane; kk < W; kk += 64) sh.wcnt[wv][kk] = 0u;
-    if (near && rank == 0) sh.wcnt[wv][k] = static_cast<uint32_t>(__popcll(m));
+    if (st == 3) atomicOr(&sh.err, kErrState);
+    cand = false;
+    if (st == 0 && s.t0 != 0u) cand = philox(q.id, step32, 0u, 0u, s.key0, s.key1).x < s.t0;
+    return st;
+  };
+  // A candidate's entry (input order within the wave's piece) for k_collide; lanes that
+  // are not candidates write the sink entry, so the stores are not branched over.
+  // A deferred candidate (a far mover) keeps its place in the list but its entry is
+  // written when its output index is known.
+  auto list_candidate = [&](bool cand, bool defer, uint32_t dst, const Part<P>& q, int d,
+                            real pos, real vxn) {
     const unsigned long long cm = __ballot(cand);
-    if (lane == 0) sh.cq[wv] = static_cast<uint32_t>(__popcll(cm));
-    __syncthreads();  // per-wave slot and candidate counts written
-    for (int kk = tid; kk < W; kk += kWG) {
-      uint32_t run = sh.off[kk];
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = sh.wcnt[w][kk];
-        sh.wcnt[w][kk] = run;
-        run += c;
-      }
-      sh.off[kk] = run;
-    }
-    if (tid == kWG - 1) {
-      uint32_t run = sh.cq[kWaves];
-      for (int w = 0; w < kWaves; ++w) {
-        const uint32_t c = sh.cq[w];
-        sh.cq[w] = run;
-        run += c;
-      }
-      sh.cq[kWaves] = run;
-    }
-    __syncthreads();  // output offsets and queue positions known
-    if (st == 0) {
-      uint32_t dst;
-      bool ok;
-      if (near) {
-        dst = sh.wcnt[wv][k] + static_cast<uint32_t>(rank);
-        ok = true;
-      } else {
-        ok = far_ok;
-        dst = ok ? s.far_dest[i] : 0u;
-      }
-      if (ok && dst >= n_out) {
-        atomicOr(sim.error, kErrState);
-        ok = false;
-      }
-      if (ok) store_record<P>(out, dst, d, pos, vxn, q.vy, q.vz, q.id);
-      if (cand) {  // the tile's candidates, in input order, for k_collide
-        const uint32_t e = r.lo + sh.cq[wv] + static_cast<uint32_t>(__popcll(cm & lt));
-        if (e < s.cap) s.cand[e] = make_uint4(ok ? dst : kNoDest, q.id, b0.y, b0.z);
-      }
-      if (!near && ok) far_deposit<P>(s, d, pos);
-    }
-    // deposit of the near particles into this wave's window
-    real w0 = real(0), w1 = real(0);
-    if (near) deposit_weights<P>(pos, w0, w1);
-    const unsigned long long lead = __ballot(near && rank == 0);
-    if (__popcll(lead) <= kReduceSlots) {
-      unsigned long long rem = lead;
-      while (rem) {
-        const int L = __ffsll(static_cast<long long>(rem)) - 1;
-        const int key = __shfl(k, L, 64);
-        const bool mine = near && k == key;
-        const real a = wave_sum<real>(mine ? w0 : real(0));
-        const real b = wave_sum<real>(mine ? w1 : real(0));
-        if (lane == L) {
-          sh.dep[wv][key] += a;
-          sh.dep[wv][key + 1] += b;
+    const uint32_t e = cand ? wr.lo + n_cand + static_cast<uint32_t>(__popcll(cm & lt)) : sink;
+    const uint32_t ew = defer ? sink : e;
+    s.cand[ew] = make_uint4(dst, q.id, static_cast<uint32_t>(d), 0u);
+    cpos[ew] = pos;
+    cvx[ew] = vxn;
+    cvy[ew] = q.vy;
+    cvz[ew] = q.vz;
+    n_cand += static_cast<uint32_t>(__popcll(cm));
+    return e;
+  };
+  auto write_candidate = [&](uint32_t e, uint32_t dst, uint32_t id, int d, real pos, real vx,
+                             real vy, real vz) {
+    s.cand[e] = make_uint4(dst, id, static_cast<uint32_t>(d), 0u);
+    cpos[e] = pos;
+    cvx[e] = vx;
+    cvy[e] = vy;
+    cvz[e] = vz;
+  };
+
+  if (!r.tail) {
+    // Far movers (beyond the window) wait in a per-wave LDS queue until the loop is
+    // done: their output index is a global load, and a load inside the loop would make
+    // the loop wait for the next chunk's loads too.
+    uint32_t qn = 0;  // wave-uniform
+    auto flush = [&]() {  // one queue entry per lane (the queue holds at most 64)
+      const uint32_t j = static_cast<uint32_t>(lane);
+      if (j < qn) {
+        const uint32_t* f = sh.fq[wv][j];
+        const uint32_t i = f[0];
+        const int d = static_cast<int>(f[1]);
+        real pos, vx, vy, vz;
+        if constexpr (std::is_same<P, P32>::value) {
+          pos = __uint_as_float(f[2]);
+          vx = __uint_as_float(f[3]);
+          vy = __uint_as_float(f[4]);
+          vz = __uint_as_float(f[5]);
+        } else {
+          pos = sh.fqd[wv][j][0];
+          vx = sh.fqd[wv][j][1];
+          vy = sh.fqd[wv][j][2];
+          vz = sh.fqd[wv][j][3];
         }
-        rem &= rem - 1ull;
+        uint32_t dst = far_ok && i < s.cap ? s.far_dest[i] : kNoDest;
+        if (dst != kNoDest && dst >= n_out) {
+          atomicOr(&sh.err, kErrState);
+          dst = kNoDest;
+        }
+        if (dst != kNoDest) {
+          store_record<P>(out, dst, d, pos, vx, vy, vz, f[6]);
+          far_deposit<P>(s, d, pos);
+        }
+        if (f[7] != kNoDest) write_candidate(f[7], dst, f[6], d, pos, vx, vy, vz);
       }
-    } else if (near) {
-      atomicAdd(&sh.dep[wv][k], w0);
-      atomicAdd(&sh.dep[wv][k + 1], w1);
-    }
+      qn = 0;
+    };
+    const int nbits = key_bits(W);
+    stream_range<Part<P>, MainU<P>::value>(
+        wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
+          int d = 0;
+          real pos = real(0), vxn = real(0);
+          bool cand;
+          const int st = push_and_test(std::false_type{}, q, valid, d, pos, vxn, cand);
+          const int k = st == 0 ? window_slot(s, tile, d) : -1;
+          const bool near = k >= 0;
+          // stable rank inside this wave's unit of the order
+          const unsigned long long m = match_key(k, near, nbits);
+          const int rank = __popcll(m & lt);
+          uint32_t dst = sink;
+          if (near) dst = sh.off[wv][k] + static_cast<uint32_t>(rank);
+          if (near && rank == 0) sh.off[wv][k] = dst + static_cast<uint32_t>(__popcll(m));
+          if (near && dst >= n_out) {
+            atomicOr(&sh.err, kErrState);
+            dst = sink;
+          }
+          store_record<P>(out, dst, d, pos, vxn, q.vy, q.vz, q.id);
+          const bool far = st == 0 && !near;
+          const uint32_t e = list_candidate(cand, far, near ? dst : kNoDest, q, d, pos, vxn);
+          const unsigned long long fm = __ballot(far);
+          if (fm) {
+            if (qn + static_cast<uint32_t>(__popcll(fm)) > static_cast<uint32_t>(kFarQ)) flush();
+            if (far) {
+              const uint32_t j = qn + static_cast<uint32_t>(__popcll(fm & lt));
+              uint32_t* f = sh.fq[wv][j];
+              f[0] = i;
+              f[1] = static_cast<uint32_t>(d);
+              if constexpr (std::is_same<P, P32>::value) {
+                f[2] = __float_as_uint(pos);
+                f[3] = __float_as_uint(vxn);
+                f[4] = __float_as_uint(q.vy);
+                f[5] = __float_as_uint(q.vz);
+              } else {
+                sh.fqd[wv][j][0] = pos;
+                sh.fqd[wv][j][1] = vxn;
+                sh.fqd[wv][j][2] = q.vy;
+                sh.fqd[wv][j][3] = q.vz;
+              }
+              f[6] = q.id;
+              f[7] = cand ? e : kNoDest;
+            }
+            qn += static_cast<uint32_t>(__popcll(fm));
+          }
+          // deposit of the near particles into this wave's window (m groups them by slot)
+          real w0 = real(0), w1 = real(0);
+          if (near) deposit_weights<P>(pos, w0, w1);
+          const unsigned long long lead = __ballot(near && rank == 0);
+          if (__popcll(lead) <= kReduceSlots) {
+            unsigned long long rem = lead;
+            while (rem) {
+              const int L = __ffsll(static_cast<long long>(rem)) - 1;
+              const int key = __shfl(k, L, 64);
+              const bool mine = near && k == key;
+              const real a = wave_sum<real>(mine ? w0 : real(0));
+              const real b = wave_sum<real>(mine ? w1 : real(0));
+              if (lane == L) {
+                sh.dep[wv][key] += a;
+                sh.dep[wv][key + 1] += b;
+              }
+              rem &= rem - 1ull;
+            }
+          } else if (near) {
+            atomicAdd(&sh.dep[wv][k], w0);
+            atomicAdd(&sh.dep[wv][k + 1], w1);
+          }
+        });
+    if (qn) flush();
+  } else {
+    // Tail tile: rank per cell against this wave's global tail row, one returning atomic
+    // per (cell, chunk) by the group leader; deposits go to the far array.
+    uint32_t GM* trow = s.trel + static_cast<size_t>((tile - s.n_tiles) * kWaves + wv) * s.n_cells;
+    const int nbits = key_bits(s.n_cells);
+    stream_range<Part<P>, MainU<P>::value>(
+        wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
+          int d = 0;
+          real pos = real(0), vxn = real(0);
+          bool cand;
+          const int st = push_and_test(std::true_type{}, q, valid, d, pos, vxn, cand);
+          const bool act = st == 0;
+          const unsigned long long mc = match_key(d, act, nbits);
+          const int rank = __popcll(mc & lt);
+          uint32_t old = 0u;
+          if (act && rank == 0) old = atomicAdd(&trow[d], static_cast<uint32_t>(__popcll(mc)));
+          const int leader = act ? __ffsll(static_cast<long long>(mc)) - 1 : lane;
+          old = __shfl(old, leader, 64);
+          uint32_t dst = kNoDest;
+          if (act) {
+            dst = s.base[d] + old + static_cast<uint32_t>(rank);
+            if (dst >= n_out) {
+              atomicOr(&sh.err, kErrState);
+              dst = kNoDest;
+            }
+          }
+          store_record<P>(out, dst == kNoDest ? sink : dst, d, pos, vxn, q.vy, q.vz, q.id);
+          list_candidate(cand, false, dst, q, d, pos, vxn);
+          if (dst != kNoDest) far_deposit<P>(s, d, pos);
+        });
   }
+  if (lane == 0) s.cand_cnt[tile * kWaves + wv] = n_cand;
   __syncthreads();
   // tile epilogue
   if (!r.tail) {
-    real* part = static_cast<real*>(s.partial) + static_cast<size_t>(tile) * (W + 1);
+    real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (W + 1);
     for (int k = tid; k <= W; k += kWG) part[k] = sh.dep[0][k] + sh.dep[1][k] + sh.dep[2][k] + sh.dep[3][k];
   }
   if (tid == 0) {
-    s.cand_cnt[tile] = sh.cq[kWaves];
     s.tile_first[tile] = r.lo;
+    if (sh.err) atomicOr(sim.error, sh.err);
     if (sh.abs_cnt[0]) atomicAdd(&s.absorbed[0], static_cast<unsigned long long>(sh.abs_cnt[0]));
     if (sh.abs_cnt[1]) atomicAdd(&s.absorbed[1], static_cast<unsigned long long>(sh.abs_cnt[1]));
     if (sh.abs_cnt[0]) atomicAdd(&s.absorbed_energy[0], sh.abs_e[0]);
@@ -792,23 +1084,35 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
 // ====================================================================================
 // k_collide: modified null-collision MCC (Sec. 3.8, eq. null_collision) of the candidates
 // k_main found (word 0 of the particle's Philox block 0 below floor(P0 2^32)).  One
-// workgroup per tile takes the tile's candidates in input order, 256 at a time, so the
-// collision path runs on full waves.  The particle's record was already scattered to
-// its sorted place; the post-collision velocity is written there.  Births are staged in
-// the order of their parents (= input order) and deposited; k_finalize appends them.
+// workgroup per tile takes the tile's candidates in input order (its waves' lists one
+// after the other), 256 at a time, so the collision path runs on full waves.  k_main
+// stored each candidate's post-push state beside its sorted slot; the post-collision
+// velocity is written to that slot.  Births are staged in the order of their parents
+// (= input order) and deposited; k_finalize appends them.
 // ====================================================================================
 template <class P>
 __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
-  const SpeciesDev& s = sim.sp[tt.x];
+  const SpeciesDev s = sim.sp[tt.x];
   const unsigned long long step = *sim.step;
   const uint32_t step32 = static_cast<uint32_t>(step);
   const int p = static_cast<int>(step & 1ull), pq = p ^ 1;
   const int tile = tt.y;
   const TileRange r = tile_range(s, tile, p);
-  const uint32_t n = s.cand_cnt[tile];
+  uint32_t seg_lo[kWaves], seg_pre[kWaves + 1];
+  seg_pre[0] = 0u;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    seg_lo[w] = wave_range(r, w).lo;
+    seg_pre[w + 1] = seg_pre[w] + s.cand_cnt[tile * kWaves + w];
+  }
+  const uint32_t n = seg_pre[kWaves];
+  if (n == 0u) {
+    if (threadIdx.x == 0) s.birth_cnt[tile] = 0u;
+    return;
+  }
   __shared__ uint32_t bq[kWaves + 1];
   __shared__ uint32_t coll[3];
   __shared__ uint32_t births;
@@ -818,36 +1122,44 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     births = 0u;
   }
   __syncthreads();
-  void* const* out = s.fld[pq];
-  const SpeciesDev* ion = s.sp == 0 ? &sim.sp[tt.x + 1] : nullptr;
-  real* part = static_cast<real*>(s.partial) + static_cast<size_t>(tile) * (s.W + 1);
+  const RecPtr out = rec_of(sim.sp[tt.x].fld[pq]);
+  const RecPtr stage_e = rec_of(sim.sp[tt.x].stage[0]);
+  const RecPtr stage_i = rec_of(sim.sp[tt.x].stage[1]);
+  const SpeciesDev ion = sim.sp[s.sp == 0 ? tt.x + 1 : tt.x];  // used by electron tiles
+  real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (s.W + 1);
   for (uint32_t b = 0; b < n; b += kWG) {
     const uint32_t e = b + tid;
     bool born = false;
     int d = 0;
     real pos = real(0);
     real vs[3] = {real(0), real(0), real(0)}, vi[3] = {real(0), real(0), real(0)};
-    const uint4 c = (e < n && r.lo + e < s.cap) ? s.cand[r.lo + e] : make_uint4(kNoDest, 0u, 0u, 0u);
-    const uint32_t dst = c.x;
-    if (dst != kNoDest && dst < s.cap) {
-      if constexpr (std::is_same<P, P32>::value) {
-        d = static_cast<const int*>(out[F32_CELL])[dst];
-        pos = static_cast<const float*>(out[F32_OFF])[dst];
-      } else {
-        pos = static_cast<const double*>(out[F64_X])[dst];
-        d = static_cast<int>(floor(pos));
-      }
-      real v[3];
-      v[0] = static_cast<const real*>(out[F_VX])[dst];
-      v[1] = static_cast<const real*>(out[F_VY])[dst];
-      v[2] = static_cast<const real*>(out[F_VZ])[dst];
-      const int ch = collide<P>(s, c.y, step32, c.z, c.w, v, vs, vi);
-      if (ch > 0) {
-        atomicAdd(&coll[ch - 1], 1u);
-        static_cast<real*>(out[F_VX])[dst] = v[0];
-        static_cast<real*>(out[F_VY])[dst] = v[1];
-        static_cast<real*>(out[F_VZ])[dst] = v[2];
-        born = s.sp == 0 && ch == 3;
+    if (e < n) {
+      int w = 0;
+#pragma unroll
+      for (int k = 1; k < kWaves; ++k) w += e >= seg_pre[k] ? 1 : 0;
+      const uint32_t idx = seg_lo[w] + (e - seg_pre[w]);
+      const uint4 c = idx < s.cap ? s.cand[idx] : make_uint4(kNoDest, 0u, 0u, 0u);
+      const uint32_t dst = c.x;
+      if (dst != kNoDest && dst < s.cap) {
+        pos = static_cast<const real GM*>(s.cand_f[0])[idx];
+        real v[3];
+        v[0] = static_cast<const real GM*>(s.cand_f[1])[idx];
+        v[1] = static_cast<const real GM*>(s.cand_f[2])[idx];
+        v[2] = static_cast<const real GM*>(s.cand_f[3])[idx];
+        if constexpr (std::is_same<P, P32>::value) {
+          d = static_cast<int>(c.z);
+        } else {
+          d = static_cast<int>(floor(pos));
+        }
+        const uint4 b0 = philox(c.y, step32, 0u, 0u, s.key0, s.key1);
+        const int ch = collide<P>(s, c.y, step32, b0.y, b0.z, v, vs, vi);
+        if (ch > 0) {
+          atomicAdd(&coll[ch - 1], 1u);
+          static_cast<real GM*>(out[F_VX])[dst] = v[0];
+          static_cast<real GM*>(out[F_VY])[dst] = v[1];
+          static_cast<real GM*>(out[F_VZ])[dst] = v[2];
+          born = s.sp == 0 && ch == 3;
+        }
       }
     }
     uint32_t total;
@@ -855,8 +1167,8 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     if (born) {
       const uint32_t si = r.lo + births + pre;
       if (si < s.cap) {
-        store_record<P, false>(s.stage[0], si, d, pos, vs[0], vs[1], vs[2], 0u);
-        store_record<P, false>(s.stage[1], si, d, pos, vi[0], vi[1], vi[2], 0u);
+        store_record<P, false>(stage_e, si, d, pos, vs[0], vs[1], vs[2], 0u);
+        store_record<P, false>(stage_i, si, d, pos, vi[0], vi[1], vi[2], 0u);
         const int k = r.tail ? -1 : window_slot(s, tile, d);
         if (k >= 0) {
           real w0, w1;
@@ -866,7 +1178,7 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
         } else {
           far_deposit<P>(s, d, pos);
         }
-        far_deposit<P>(*ion, d, pos);
+        far_deposit<P>(ion, d, pos);
       } else {
         atomicOr(sim.error, kErrState);
       }
@@ -881,7 +1193,6 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
       if (coll[k]) atomicAdd(&s.collisions[k], static_cast<unsigned long long>(coll[k]));
   }
 }
-
 // ====================================================================================
 // k_finalize: one workgroup per (discharge, species).  Births are appended after the
 // sorted survivors in the order of their parents' input index (the electron tiles are
@@ -892,8 +1203,8 @@ template <class P>
 __global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
-  const SpeciesDev& s = sim.sp[blockIdx.x];
-  const SpeciesDev& se = sim.sp[blockIdx.x - s.sp];
+  const SpeciesDev s = sim.sp[blockIdx.x];
+  const SpeciesDev se = sim.sp[blockIdx.x - s.sp];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
   __shared__ uint32_t sh_fit, sh_nid;
   const unsigned long long step = *sim.step;
@@ -921,8 +1232,8 @@ __global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict_
   }
   __syncthreads();
   const uint32_t fit = sh_fit, nid = sh_nid;
-  void* const* src = se.stage[s.sp];
-  void* const* dst = s.fld[q];
+  const RecPtr src = rec_of(sim.sp[blockIdx.x - s.sp].stage[s.sp]);
+  const RecPtr dst = rec_of(sim.sp[blockIdx.x].fld[q]);
   for (uint32_t b = threadIdx.x; b < fit; b += blockDim.x) {
     int lo = 0, hi = nt;
     while (hi - lo > 1) {
@@ -936,14 +1247,14 @@ __global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict_
     int cell = 0;
     real pos;
     if constexpr (std::is_same<P, P32>::value) {
-      cell = static_cast<const int*>(src[F32_CELL])[si];
-      pos = static_cast<const float*>(src[F32_OFF])[si];
+      cell = static_cast<const int GM*>(src[F32_CELL])[si];
+      pos = static_cast<const float GM*>(src[F32_OFF])[si];
     } else {
-      pos = static_cast<const double*>(src[F64_X])[si];
+      pos = static_cast<const double GM*>(src[F64_X])[si];
     }
-    store_record<P>(dst, di, cell, pos, static_cast<const real*>(src[F_VX])[si],
-                    static_cast<const real*>(src[F_VY])[si],
-                    static_cast<const real*>(src[F_VZ])[si], nid + b);
+    store_record<P>(dst, di, cell, pos, static_cast<const real GM*>(src[F_VX])[si],
+                    static_cast<const real GM*>(src[F_VY])[si],
+                    static_cast<const real GM*>(src[F_VZ])[si], nid + b);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -974,7 +1285,7 @@ static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e
 
 void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
-  const dim3 grid((li.max_nodes + 255) / 256, li.n_spec);
+  const dim3 grid((li.max_nodes + kWaves - 1) / kWaves, li.n_spec);
   if (li.fp32) launch(k_combine<float>, grid, dim3(256), st, e0, e1, sim);
   else launch(k_combine<double>, grid, dim3(256), st, e0, e1, sim);
 }
@@ -992,7 +1303,7 @@ void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 
 void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
-  launch(k_scan_cells, dim3((li.max_cells + 255) / 256, li.n_spec), dim3(256), st, e0,
+  launch(k_scan_cells, dim3((li.max_cells + kWaves - 1) / kWaves, li.n_spec), dim3(256), st, e0,
          static_cast<hipEvent_t>(nullptr), sim);
   launch(k_scan_base, dim3(li.n_spec), dim3(kSolveWG), st, static_cast<hipEvent_t>(nullptr),
          e1, sim);

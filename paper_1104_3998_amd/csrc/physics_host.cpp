@@ -166,7 +166,10 @@ void choose_tiles(const pic_config& c, TileChoice tc[2]) {
     tc[s].D = D;
     tc[s].W = C + 2 * D;
     tc[s].n_tiles = (N + C - 1) / C;
-    tc[s].n_tail = c.tail_groups > 0 ? static_cast<int>(c.tail_groups) : 4;
+    // tail tiles: about one per 128 cell tiles (births are well under 1% of a step's
+    // particles), each with a global rank row per wave over all cells
+    tc[s].n_tail = c.tail_groups > 0 ? static_cast<int>(c.tail_groups)
+                                     : std::max(1, std::min(16, tc[s].n_tiles / 128));
   }
 }
 

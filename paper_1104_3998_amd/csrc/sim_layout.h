@@ -13,6 +13,23 @@
 
 namespace fspic {
 
+// Device code sees the descriptors' array pointers as global-memory pointers, so loads and
+// stores through them compile to global_* instructions.  Through a generic pointer they
+// would be flat_* instructions, which also count against the LDS wait counter and make
+// every LDS access in a loop wait for the loads in flight.  Host code sees plain pointers
+// of the same size and layout.
+// The descriptors themselves are read through constant-address-space pointers: they do not
+// change during a launch, and the compiler then reads them with scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FSPIC_GLOBAL __attribute__((address_space(1)))
+#define FSPIC_CONST __attribute__((address_space(4)))
+#else
+#define FSPIC_GLOBAL
+#define FSPIC_CONST
+#endif
+#define GM FSPIC_GLOBAL
+#define CM FSPIC_CONST
+
 constexpr int kWG = 256;             // threads per workgroup of the particle kernels
 constexpr int kWaves = kWG / 64;     // wave64
 constexpr int kMaxWindow = 256;      // histogram window W = C + 2D (8-bit slot keys)
@@ -36,44 +53,48 @@ enum : int { F64_X = 0 };
 struct SpeciesDev {
   int32_t ds, sp, n_cells, periodic;
   int32_t C, D, W, n_tiles;        // cell tiles: tile t owns cells [tC, tC + C)
-  int32_t tile_base;               // first global workgroup index of the cell tiles
-  int32_t n_tail, tail_base;       // workgroups that take the unsorted tail (births)
+  int32_t n_tail;                  // tail tiles: the unsorted births at the end of the array
   int32_t n_nodes;
   uint32_t cap, far_cap;
   // particle arrays: [buffer][field]; FP32 cell+offset: cell, off, vx, vy, vz, id;
   // FP64: x, (unused), vx, vy, vz, id
-  void* fld[2][6];
+  void GM* fld[2][6];
   // birth staging (electron species only): [0] secondary electrons, [1] new ions;
   // fields as in fld
-  void* stage[2][6];
-  uint32_t* n_total;        // [2] particles in buffer b
-  uint32_t* n_sorted;       // [2] length of the cell-sorted prefix of buffer b
-  uint32_t* next_id;        // [1]
-  uint32_t* cell_start;     // [2][n_cells + 1] first index of each cell in the sorted prefix
-  uint32_t* hist;           // [n_tiles * W] post-push cell histogram of each tile
-  uint32_t* tilerel;        // [n_tiles * W] offset of tile t inside cell c, relative to base[c]
-  void* partial;            // [n_tiles * (W + 1)] tile deposit windows (float or double)
-  double* far_w;            // [n_nodes] deposits of far movers and births
-  uint32_t* far_count;      // [1]
-  uint4* far_list;          // [far_cap] (cell, index, source tile, 0)
-  uint4* far_grouped;       // [far_cap] far list grouped by cell
-  uint32_t* far_cell_cnt;   // [n_cells]
-  uint32_t* far_fill;       // [n_cells]
-  uint32_t* far_base;       // [n_cells]
-  uint32_t* base;           // [n_cells] first output index of each cell
-  uint32_t* far_dest;       // [cap] output index of each far mover, by input index
-  uint4* cand;              // [cap] MCC candidates (output slot, id, channel words), stored
-                            // in each tile's input-index range
-  uint32_t* cand_cnt;       // [n_tiles + n_tail]
-  uint32_t* birth_cnt;      // [n_tiles + n_tail] births of each electron tile
-  uint32_t* tile_first;     // [n_tiles + n_tail] first input index of each tile
-  uint32_t* birth_base;     // [n_tiles + n_tail + 1] exclusive scan of the electron births
-  unsigned long long* absorbed;   // [2] per wall (0 left, 1 right)
-  double* absorbed_energy;        // [2] eV
-  unsigned long long* births;     // [1]
-  unsigned long long* collisions; // [3]
-  double* ke_sum;                 // [4] sum vx^2, vy^2, vz^2, vx (diagnostic steps)
-  unsigned long long* psteps;     // [1] particles stepped, summed over steps
+  void GM* stage[2][6];
+  uint32_t GM* n_total;        // [2] particles in buffer b
+  uint32_t GM* n_sorted;       // [2] length of the cell-sorted prefix of buffer b
+  uint32_t GM* next_id;        // [1]
+  uint32_t GM* cell_start;     // [2][n_cells + 1] first index of each cell in the sorted prefix
+  // A tile's index range is split into kWaves contiguous sub-ranges, one per wave, in
+  // order; each (tile, wave) keeps its own histogram row so the waves never synchronise.
+  uint32_t GM* hist;           // [n_tiles * kWaves * W] post-push cell histogram per (tile, wave)
+  uint32_t GM* tilerel;        // [n_tiles * kWaves * W] offset of (tile, wave) in cell c from base[c]
+  uint32_t GM* thist;          // [n_tail * kWaves * n_cells] post-push cell counts per tail row
+  uint32_t GM* trel;           // [n_tail * kWaves * n_cells] running offset of a tail row in cell c
+  void GM* partial;            // [n_tiles * (W + 1)] tile deposit windows (float or double)
+  double GM* far_w;            // [n_nodes] deposits of far movers and births
+  uint32_t GM* far_count;      // [1]
+  uint4 GM* far_list;          // [far_cap] far movers of the cell tiles: (cell, index, tile, 0)
+  uint4 GM* far_grouped;       // [far_cap] far list grouped by cell
+  uint32_t GM* far_cell_cnt;   // [n_cells]
+  uint32_t GM* far_fill;       // [n_cells]
+  uint32_t GM* far_base;       // [n_cells]
+  uint32_t GM* base;           // [n_cells] first output index of each cell
+  uint32_t GM* far_dest;       // [cap] output index of each far mover, by input index
+  uint4 GM* cand;              // [cap] MCC candidates: (output slot, id, cell, 0), stored in the
+                            // input-index range of the wave that found them, in input order
+  void GM* cand_f[4];          // [cap] each: post-push position word, vx, vy, vz of a candidate
+  uint32_t GM* cand_cnt;       // [(n_tiles + n_tail) * kWaves] candidates per (tile, wave)
+  uint32_t GM* birth_cnt;      // [n_tiles + n_tail] births of each electron tile
+  uint32_t GM* tile_first;     // [n_tiles + n_tail] first input index of each tile
+  uint32_t GM* birth_base;     // [n_tiles + n_tail + 1] exclusive scan of the electron births
+  unsigned long long GM* absorbed;   // [2] per wall (0 left, 1 right)
+  double GM* absorbed_energy;        // [2] eV
+  unsigned long long GM* births;     // [1]
+  unsigned long long GM* collisions; // [3]
+  double GM* ke_sum;                 // [4] sum vx^2, vy^2, vz^2, vx (diagnostic steps)
+  unsigned long long GM* psteps;     // [1] particles stepped, summed over steps
   // physics (normalised units)
   double kappa;
   float kappa_f;
@@ -82,7 +103,7 @@ struct SpeciesDev {
   uint32_t key0, key1;
   int32_t xsec;
   double sigma_const;
-  uint32_t* gsort_hist;     // [n_gtiles * n_cells] general sort scratch (initial sort)
+  uint32_t GM* gsort_hist;     // [n_gtiles * n_cells] general sort scratch (initial sort)
   // initial load
   uint32_t n_init;
   int32_t load_kind, lang_mode;
@@ -91,16 +112,16 @@ struct SpeciesDev {
 
 struct DischargeDev {
   int32_t n_cells, periodic, n_nodes, spec0;
-  double* w[2];             // current node weights of electrons and ions
-  double* phi;
-  double* E64;
-  float* E32;
-  double* acc_w[2];
-  double* acc_phi;
-  double* scratch;          // [n_nodes] solver scratch
-  unsigned long long* acc_count;
-  unsigned long long* eedf;          // [eedf_bins + 1]
-  unsigned long long* eedf_samples;
+  double GM* w[2];             // current node weights of electrons and ions
+  double GM* phi;
+  double GM* E64;
+  float GM* E32;
+  double GM* acc_w[2];
+  double GM* acc_phi;
+  double GM* scratch;          // [n_nodes] solver scratch
+  unsigned long long GM* acc_count;
+  unsigned long long GM* eedf;          // [eedf_bins + 1]
+  unsigned long long GM* eedf_samples;
   int32_t eedf_bins, diag_every;
   double eedf_inv_width;
   double vhat_amp, phase_per_step;
@@ -108,13 +129,13 @@ struct DischargeDev {
 };
 
 struct SimDev {
-  unsigned long long* step;
-  uint32_t* error;
-  uint32_t* fin_count;       // workgroups of the finalize kernel done this step
+  unsigned long long GM* step;
+  uint32_t GM* error;
+  uint32_t GM* fin_count;       // workgroups of the finalize kernel done this step
   int32_t n_ds, n_spec, total_tiles, max_nodes;
-  DischargeDev* ds;
-  SpeciesDev* sp;
-  int2* tile_table;          // workgroup -> (species index, local tile)
+  const DischargeDev CM* ds;
+  const SpeciesDev CM* sp;
+  const int2 CM* tile_table;  // workgroup -> (species index, local tile)
 };
 
 }  // namespace fspic
