@@ -59,7 +59,7 @@ typedef struct pic_config {
   uint32_t periodic;         /* 1: periodic box; 0: absorbing electrodes at x = 0 and L */
   uint32_t n_cells;          /* N grid cells (bounded: N + 1 nodes, periodic: N nodes) */
   uint64_t n_e0, n_i0;       /* initial macro-particles per species */
-  uint64_t capacity_e, capacity_i; /* particle array capacity per species (< 2^31) */
+  uint64_t capacity_e, capacity_i; /* particle array capacity per species (< 2^26) */
   double length_m, dt_s, n0_m3, te_ev, ti_ev, mass_i_amu;
   double v0_volt, freq_hz;   /* electrode at x = 0 driven V0 sin(2 pi f t); x = L grounded */
   double gas_pa, gas_k;      /* background gas */

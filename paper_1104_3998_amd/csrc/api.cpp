@@ -151,16 +151,20 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       // particle and candidate arrays hold one element past the capacity: a sink that
       // lanes without a record to store write to, so that stores are not branched over
       const size_t cap1 = static_cast<size_t>(cap) + 1;
-      for (int b = 0; b < 2; ++b) {
-        if (fp32) {
-          S.fld[b][F32_CELL] = cv.take<int>(cap1);
-          S.fld[b][F32_OFF] = cv.take<float>(cap1);
-        } else {
-          S.fld[b][F64_X] = cv.take<double>(cap1);
-          S.fld[b][1] = nullptr;
+      // the two buffers of a field are one allocation, buffer 1 a fixed distance above
+      // buffer 0, so the kernels reach both from one base pointer
+      const size_t st4 = align_up(4 * cap1, 256), st8 = align_up(8 * cap1, 256);
+      S.bstride4 = static_cast<uint32_t>(st4);
+      S.bstride8 = static_cast<uint32_t>(st8);
+      for (int f = 0; f < 6; ++f) {
+        if (!fp32 && f == 1) {
+          S.fld[0][f] = S.fld[1][f] = nullptr;
+          continue;
         }
-        for (int f = F_VX; f <= F_VZ; ++f) S.fld[b][f] = cv.take<char>(rs * cap1);
-        S.fld[b][F_ID] = cv.take<uint32_t>(cap1);
+        const size_t st = (fp32 || f == F_ID) ? st4 : st8;
+        char* pair = cv.take<char>(2 * st);
+        S.fld[0][f] = pair;
+        S.fld[1][f] = pair ? pair + st : nullptr;
       }
       if (s == 0) {
         for (int b = 0; b < 2; ++b) {
@@ -194,14 +198,14 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.base = cv.take<uint32_t>(N);
       S.far_dest = cv.take<uint32_t>(cap);
       const int ntt = tc.n_tiles + tc.n_tail;
-      S.cand = cv.take<uint4>(cap1);
-      for (int f = 0; f < 4; ++f) S.cand_f[f] = cv.take<char>(rs * cap1);
+      S.cand = cv.take<char>((fp32 ? 32 : 48) * cap1);
       S.cand_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
       S.birth_cnt = cv.take<uint32_t>(ntt);
       S.tile_first = cv.take<uint32_t>(ntt);
       // births of both species are ranked over the electron tiles
       const int ntt_e = pl->tiles[2 * d].n_tiles + pl->tiles[2 * d].n_tail;
       S.birth_base = cv.take<uint32_t>(std::max(ntt, ntt_e) + 1);
+      S.fin = cv.take<uint32_t>(2);
       S.absorbed = cv.take<unsigned long long>(2);
       S.absorbed_energy = cv.take<double>(2);
       S.births = cv.take<unsigned long long>(1);

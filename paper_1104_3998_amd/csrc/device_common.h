@@ -289,6 +289,21 @@ __device__ __forceinline__ int window_slot(const SpeciesDev& s, int t, int d) {
 // ------------------------------------------------------------------------------------
 // Wave-level helpers.
 // ------------------------------------------------------------------------------------
+// Element i of a global array, addressed by a 32-bit byte offset from the array's base.
+// Every array of the library is smaller than 4 GiB (the capacities are checked on the
+// host), and in this form the base stays in scalar registers and the memory instruction
+// takes the 32-bit offset (no 64-bit address arithmetic per access).
+template <class T>
+__device__ __forceinline__ T ldg(const void GM* base, uint32_t i) {
+  return *reinterpret_cast<const T GM*>(reinterpret_cast<const char GM*>(base) +
+                                        i * static_cast<uint32_t>(sizeof(T)));
+}
+
+template <class T>
+__device__ __forceinline__ void stg(void GM* base, uint32_t i, T v) {
+  *reinterpret_cast<T GM*>(reinterpret_cast<char GM*>(base) + i * static_cast<uint32_t>(sizeof(T))) = v;
+}
+
 // Index of this thread's wave in the workgroup, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
@@ -297,6 +312,11 @@ __device__ __forceinline__ int wave_id() {
 __device__ __forceinline__ unsigned long long lanes_below() {
   const int lane = threadIdx.x & 63;
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ unsigned long long lanes_above() {
+  const int lane = threadIdx.x & 63;
+  return lane == 63 ? 0ull : (~0ull << (lane + 1));
 }
 
 // Mask of the active lanes whose key equals this lane's key (keys < 2^nbits); valid for
@@ -357,10 +377,11 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T& total) {
   return ex;
 }
 
-// In-place exclusive scan of a[0..n) by one workgroup; returns the total.
+// In-place exclusive scan of a[0..n) by one workgroup; returns the total.  The barriers
+// make the workgroup's own global stores visible to it (its waves share one CU); no
+// device-scope fence, which on this GPU writes back the whole L2.
 template <class T, class Ptr>
 __device__ T array_exclusive_scan(Ptr a, int n, T* lds) {
-  __threadfence();
   __syncthreads();
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per;
@@ -374,7 +395,6 @@ __device__ T array_exclusive_scan(Ptr a, int n, T* lds) {
     a[i] = run;
     run = run + v;
   }
-  __threadfence();
   __syncthreads();
   return total;
 }

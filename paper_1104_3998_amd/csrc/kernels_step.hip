@@ -27,18 +27,113 @@ namespace fspic {
 struct P32 {};
 struct P64 {};
 
-// The six field pointers of one particle array (or staging set), read once per launch from
-// the descriptor so that they live in scalar registers for the whole particle loop.
+// One particle array (or staging set) as the kernels address it: the field pointers of
+// buffer 0 (in scalar registers for the whole particle loop) and the byte distance to the
+// array wanted, so that the two buffers of a field share one base pointer and differ only
+// in a 32-bit offset (boff4 for 4-byte fields, boff8 for 8-byte ones).
 struct RecPtr {
   void GM* f[6];
-  __device__ __forceinline__ void GM* operator[](int k) const { return f[k]; }
+  uint32_t boff4, boff8;
 };
 
-__device__ __forceinline__ RecPtr rec_of(void GM* const CM* f) {
+// buffer b of the species' particle arrays
+__device__ __forceinline__ RecPtr rec_buf(const SpeciesDev CM* s, int b) {
   RecPtr r;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) r.f[k] = f[k];
+  for (int k = 0; k < 6; ++k) r.f[k] = s->fld[0][k];
+  r.boff4 = b ? s->bstride4 : 0u;
+  r.boff8 = b ? s->bstride8 : 0u;
   return r;
+}
+
+// a birth staging set (its own pointers)
+__device__ __forceinline__ RecPtr rec_stage(const SpeciesDev CM* s, int k6) {
+  RecPtr r;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.f[k] = s->stage[k6][k];
+  r.boff4 = r.boff8 = 0u;
+  return r;
+}
+
+// element at a 32-bit byte offset from a field's base
+template <class T>
+__device__ __forceinline__ T ldo(const void GM* base, uint32_t off) {
+  return *reinterpret_cast<const T GM*>(reinterpret_cast<const char GM*>(base) + off);
+}
+
+template <class T>
+__device__ __forceinline__ void sto(void GM* base, uint32_t off, T v) {
+  *reinterpret_cast<T GM*>(reinterpret_cast<char GM*>(base) + off) = v;
+}
+
+template <class P>
+struct Part0;
+template <>
+struct Part0<P32> {
+  using real = float;
+};
+template <>
+struct Part0<P64> {
+  using real = double;
+};
+
+// byte offset of element i of a real-valued field of the layout P
+template <class P>
+__device__ __forceinline__ uint32_t real_off(const RecPtr& f, uint32_t i);
+template <>
+__device__ __forceinline__ uint32_t real_off<P32>(const RecPtr& f, uint32_t i) {
+  return f.boff4 + i * 4u;
+}
+template <>
+__device__ __forceinline__ uint32_t real_off<P64>(const RecPtr& f, uint32_t i) {
+  return f.boff8 + i * 8u;
+}
+
+// One MCC candidate record: output slot, id, post-push cell, position word and velocity.
+// FP32: two 16-byte halves (slot, id, cell, offset bits) (vx, vy, vz, -); FP64: three
+// (slot, id, cell, -) (x, vx) (vy, vz).
+template <class P>
+__device__ __forceinline__ void cand_store(void GM* base, uint32_t e, uint32_t dst,
+                                           uint32_t id, int d, typename Part0<P>::real pos,
+                                           typename Part0<P>::real vx,
+                                           typename Part0<P>::real vy,
+                                           typename Part0<P>::real vz) {
+  if constexpr (std::is_same<P, P32>::value) {
+    const uint32_t o = e * 32u;
+    sto<uint4>(base, o, make_uint4(dst, id, static_cast<uint32_t>(d), __float_as_uint(pos)));
+    sto<float4>(base, o + 16u, make_float4(vx, vy, vz, 0.0f));
+  } else {
+    const uint32_t o = e * 48u;
+    sto<uint4>(base, o, make_uint4(dst, id, static_cast<uint32_t>(d), 0u));
+    sto<double2>(base, o + 16u, make_double2(pos, vx));
+    sto<double2>(base, o + 32u, make_double2(vy, vz));
+  }
+}
+
+template <class P>
+__device__ __forceinline__ uint4 cand_load(const void GM* base, uint32_t e,
+                                           typename Part0<P>::real& pos,
+                                           typename Part0<P>::real v[3]) {
+  if constexpr (std::is_same<P, P32>::value) {
+    const uint32_t o = e * 32u;
+    const uint4 a = ldo<uint4>(base, o);
+    const float4 b = ldo<float4>(base, o + 16u);
+    pos = __uint_as_float(a.w);
+    v[0] = b.x;
+    v[1] = b.y;
+    v[2] = b.z;
+    return a;
+  } else {
+    const uint32_t o = e * 48u;
+    const uint4 a = ldo<uint4>(base, o);
+    const double2 b = ldo<double2>(base, o + 16u);
+    const double2 c = ldo<double2>(base, o + 32u);
+    pos = b.x;
+    v[0] = b.y;
+    v[1] = c.x;
+    v[2] = c.y;
+    return a;
+  }
 }
 
 template <class P>
@@ -51,12 +146,13 @@ struct Part<P32> {
   float off, vx, vy, vz;
   uint32_t id;
   __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
-    cell = static_cast<const int GM*>(f[F32_CELL])[i];
-    off = static_cast<const float GM*>(f[F32_OFF])[i];
-    vx = static_cast<const float GM*>(f[F_VX])[i];
-    vy = static_cast<const float GM*>(f[F_VY])[i];
-    vz = static_cast<const float GM*>(f[F_VZ])[i];
-    id = static_cast<const uint32_t GM*>(f[F_ID])[i];
+    const uint32_t o = f.boff4 + i * 4u;
+    cell = ldo<int>(f.f[F32_CELL], o);
+    off = ldo<float>(f.f[F32_OFF], o);
+    vx = ldo<float>(f.f[F_VX], o);
+    vy = ldo<float>(f.f[F_VY], o);
+    vz = ldo<float>(f.f[F_VZ], o);
+    id = ldo<uint32_t>(f.f[F_ID], o);
   }
 };
 
@@ -66,11 +162,12 @@ struct Part<P64> {
   double x, vx, vy, vz;
   uint32_t id;
   __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
-    x = static_cast<const double GM*>(f[F64_X])[i];
-    vx = static_cast<const double GM*>(f[F_VX])[i];
-    vy = static_cast<const double GM*>(f[F_VY])[i];
-    vz = static_cast<const double GM*>(f[F_VZ])[i];
-    id = static_cast<const uint32_t GM*>(f[F_ID])[i];
+    const uint32_t o8 = f.boff8 + i * 8u;
+    x = ldo<double>(f.f[F64_X], o8);
+    vx = ldo<double>(f.f[F_VX], o8);
+    vy = ldo<double>(f.f[F_VY], o8);
+    vz = ldo<double>(f.f[F_VZ], o8);
+    id = ldo<uint32_t>(f.f[F_ID], f.boff4 + i * 4u);
   }
 };
 
@@ -83,17 +180,21 @@ __device__ __forceinline__ void store_record(const RecPtr& f, uint32_t i, int d,
                                              typename Part<P>::real vx,
                                              typename Part<P>::real vy,
                                              typename Part<P>::real vz, uint32_t id) {
+  const uint32_t o4 = f.boff4 + i * 4u;
   if constexpr (std::is_same<P, P32>::value) {
-    static_cast<int GM*>(f[F32_CELL])[i] = d;
-    static_cast<float GM*>(f[F32_OFF])[i] = pos;
+    sto<int>(f.f[F32_CELL], o4, d);
+    sto<float>(f.f[F32_OFF], o4, pos);
+    sto<float>(f.f[F_VX], o4, vx);
+    sto<float>(f.f[F_VY], o4, vy);
+    sto<float>(f.f[F_VZ], o4, vz);
   } else {
-    static_cast<double GM*>(f[F64_X])[i] = pos;
+    const uint32_t o8 = f.boff8 + i * 8u;
+    sto<double>(f.f[F64_X], o8, pos);
+    sto<double>(f.f[F_VX], o8, vx);
+    sto<double>(f.f[F_VY], o8, vy);
+    sto<double>(f.f[F_VZ], o8, vz);
   }
-  using real = typename Part<P>::real;
-  static_cast<real GM*>(f[F_VX])[i] = vx;
-  static_cast<real GM*>(f[F_VY])[i] = vy;
-  static_cast<real GM*>(f[F_VZ])[i] = vz;
-  if constexpr (kWithId) static_cast<uint32_t GM*>(f[F_ID])[i] = id;
+  if constexpr (kWithId) sto<uint32_t>(f.f[F_ID], o4, id);
 }
 
 struct TileRange {
@@ -172,6 +273,42 @@ __device__ __forceinline__ void stream_range(uint32_t lo, uint32_t hi, Load&& lo
   }
 }
 
+// The same, from the end of the range backwards: pass by pass and chunk by chunk in
+// decreasing index order (lanes inside a chunk still ascend; lanes before the start
+// re-read the first element).
+template <class T, int U, class Load, class Body>
+__device__ __forceinline__ void stream_range_rev(uint32_t lo, uint32_t hi, Load&& load,
+                                                 Body&& body) {
+  if (lo >= hi) return;
+  const int lane = static_cast<int>(threadIdx.x & 63u);
+  const int ilo = static_cast<int>(lo), ihi = static_cast<int>(hi);
+  T nxt[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) load(nxt[u], static_cast<uint32_t>(max(ihi - 64 * (u + 1) + lane, ilo)));
+  for (int b = ihi; b > ilo; b -= U * 64) {
+    T cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      load(nxt[u], static_cast<uint32_t>(max(b - 64 * (U + u + 1) + lane, ilo)));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = b - 64 * (u + 1) + lane;
+      body(cur[u], static_cast<uint32_t>(max(i, ilo)), i >= ilo);
+    }
+  }
+}
+
+// In k_main the even waves of a cell tile walk their piece backwards: each cell's output
+// sub-run of a wave is then filled from its end, and the cache lines that two neighbouring
+// sub-runs share are written by both neighbours at about the same time (at the start or
+// at the end of both passes) instead of once early and once late, when a half-written
+// line has long been written back.
+__device__ __forceinline__ bool wave_reversed(const TileRange& r, int w) {
+  return !r.tail && (w & 1) == 0;
+}
+
 // The fields the push reads (the sort pre-pass loads only these).
 template <class P>
 struct PushIn;
@@ -181,9 +318,10 @@ struct PushIn<P32> {
   int cell;
   float off, vx;
   __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
-    cell = static_cast<const int GM*>(f[F32_CELL])[i];
-    off = static_cast<const float GM*>(f[F32_OFF])[i];
-    vx = static_cast<const float GM*>(f[F_VX])[i];
+    const uint32_t o = f.boff4 + i * 4u;
+    cell = ldo<int>(f.f[F32_CELL], o);
+    off = ldo<float>(f.f[F32_OFF], o);
+    vx = ldo<float>(f.f[F_VX], o);
   }
 };
 
@@ -191,8 +329,9 @@ template <>
 struct PushIn<P64> {
   double x, vx;
   __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
-    x = static_cast<const double GM*>(f[F64_X])[i];
-    vx = static_cast<const double GM*>(f[F_VX])[i];
+    const uint32_t o8 = f.boff8 + i * 8u;
+    x = ldo<double>(f.f[F64_X], o8);
+    vx = ldo<double>(f.f[F_VX], o8);
   }
 };
 
@@ -445,7 +584,7 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   const int nbits = key_bits(W);
   __syncthreads();
   const WaveRange wr = wave_range(r, wv);
-  const RecPtr in = rec_of(sim.sp[tt.x].fld[p]);
+  const RecPtr in = rec_buf(&sim.sp[tt.x], p);
   auto load = [&](PushIn<P>& q, uint32_t i) { q.load(in, i); };
   if (!r.tail) {
     // far movers wait in a per-wave LDS queue and are appended to the far list after the
@@ -594,8 +733,7 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
       const uint32_t pos = s.far_base[v.x] + atomicAdd(&s.far_fill[v.x], 1u);
       if (pos < F) s.far_grouped[pos] = v;
     }
-    __threadfence();
-    __syncthreads();
+    __syncthreads();  // one workgroup: a barrier makes its global stores visible to it
     // the cell-tile units' offsets in cells that receive far movers from lower tiles
     for (int c = threadIdx.x; c < N; c += blockDim.x) {
       const uint32_t g = s.far_cell_cnt[c];
@@ -646,8 +784,6 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
 // and the linear deposit into its own LDS window (Sec. 3.4).  Tail tiles rank their
 // particles per cell against their global tail rows.
 // ====================================================================================
-constexpr int kReduceSlots = 4;     // up to this many distinct slots a wave reduces in
-                                    // registers; more, and it adds with LDS atomics
 constexpr uint32_t kNoDest = 0xFFFFFFFFu;
 constexpr int kFarQ = 64;           // per-wave queue of far movers (one chunk always fits)
 
@@ -832,7 +968,7 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   const int tile = tt.y;
   __shared__ MainShared<P> sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
-  const unsigned long long lt = lanes_below();
+  const unsigned long long lt = lanes_below(), gt = lanes_above();
   const bool eedf_on = s.sp == 0 && diag_step(dd, step);
   const bool far_ok = (*sim.error & kErrFarOverflow) == 0u;
   const uint32_t n_out = s.n_sorted[pq];
@@ -849,8 +985,11 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
         c %= s.n_cells;
         if (c < 0) c += s.n_cells;
       }
+      // running output index of (wave, slot): the start of its sub-run, or the end for
+      // a wave that walks backwards
+      const size_t o = (static_cast<size_t>(tile) * kWaves + w) * W + kk;
       sh.off[w][kk] = (c >= 0 && c < s.n_cells)
-                          ? s.base[c] + s.tilerel[(static_cast<size_t>(tile) * kWaves + w) * W + kk]
+                          ? s.base[c] + s.tilerel[o] + (wave_reversed(r, w) ? s.hist[o] : 0u)
                           : 0u;
     }
   }
@@ -864,12 +1003,8 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   }
   __syncthreads();
   const WaveRange wr = wave_range(r, wv);
-  const RecPtr in = rec_of(sim.sp[tt.x].fld[p]);
-  const RecPtr out = rec_of(sim.sp[tt.x].fld[pq]);
-  real GM* const cpos = static_cast<real GM*>(s.cand_f[0]);
-  real GM* const cvx = static_cast<real GM*>(s.cand_f[1]);
-  real GM* const cvy = static_cast<real GM*>(s.cand_f[2]);
-  real GM* const cvz = static_cast<real GM*>(s.cand_f[3]);
+  const RecPtr in = rec_buf(&sim.sp[tt.x], p);
+  const RecPtr out = rec_buf(&sim.sp[tt.x], pq);
   uint32_t n_cand = 0;  // candidates of this wave so far (wave-uniform)
   auto load = [&](Part<P>& q, uint32_t i) { q.load(in, i); };
 
@@ -902,26 +1037,26 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   // are not candidates write the sink entry, so the stores are not branched over.
   // A deferred candidate (a far mover) keeps its place in the list but its entry is
   // written when its output index is known.
-  auto list_candidate = [&](bool cand, bool defer, uint32_t dst, const Part<P>& q, int d,
-                            real pos, real vxn) {
+  // A backward wave fills its list from the end of its piece, so the list is always in
+  // input order: [lo, lo + n) forwards, [hi - n, hi) backwards.
+  auto list_candidate = [&](auto rev_tag, bool cand, bool defer, uint32_t dst, const Part<P>& q,
+                            int d, real pos, real vxn) {
+    constexpr bool kRev = decltype(rev_tag)::value;
     const unsigned long long cm = __ballot(cand);
-    const uint32_t e = cand ? wr.lo + n_cand + static_cast<uint32_t>(__popcll(cm & lt)) : sink;
-    const uint32_t ew = defer ? sink : e;
-    s.cand[ew] = make_uint4(dst, q.id, static_cast<uint32_t>(d), 0u);
-    cpos[ew] = pos;
-    cvx[ew] = vxn;
-    cvy[ew] = q.vy;
-    cvz[ew] = q.vz;
+    uint32_t e = sink;
+    if (cand) {
+      if constexpr (kRev)
+        e = wr.hi - 1u - n_cand - static_cast<uint32_t>(__popcll(cm & gt));
+      else
+        e = wr.lo + n_cand + static_cast<uint32_t>(__popcll(cm & lt));
+    }
+    cand_store<P>(s.cand, defer ? sink : e, dst, q.id, d, pos, vxn, q.vy, q.vz);
     n_cand += static_cast<uint32_t>(__popcll(cm));
     return e;
   };
   auto write_candidate = [&](uint32_t e, uint32_t dst, uint32_t id, int d, real pos, real vx,
                              real vy, real vz) {
-    s.cand[e] = make_uint4(dst, id, static_cast<uint32_t>(d), 0u);
-    cpos[e] = pos;
-    cvx[e] = vx;
-    cvy[e] = vy;
-    cvz[e] = vz;
+    cand_store<P>(s.cand, e, dst, id, d, pos, vx, vy, vz);
   };
 
   if (!r.tail) {
@@ -961,74 +1096,78 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       qn = 0;
     };
     const int nbits = key_bits(W);
-    stream_range<Part<P>, MainU<P>::value>(
-        wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
-          int d = 0;
-          real pos = real(0), vxn = real(0);
-          bool cand;
-          const int st = push_and_test(std::false_type{}, q, valid, d, pos, vxn, cand);
-          const int k = st == 0 ? window_slot(s, tile, d) : -1;
-          const bool near = k >= 0;
-          // stable rank inside this wave's unit of the order
-          const unsigned long long m = match_key(k, near, nbits);
-          const int rank = __popcll(m & lt);
-          uint32_t dst = sink;
-          if (near) dst = sh.off[wv][k] + static_cast<uint32_t>(rank);
-          if (near && rank == 0) sh.off[wv][k] = dst + static_cast<uint32_t>(__popcll(m));
-          if (near && dst >= n_out) {
-            atomicOr(&sh.err, kErrState);
-            dst = sink;
+    auto cell_body = [&](auto rev_tag, const Part<P>& q, uint32_t i, bool valid) {
+      constexpr bool kRev = decltype(rev_tag)::value;
+      int d = 0;
+      real pos = real(0), vxn = real(0);
+      bool cand;
+      const int st = push_and_test(std::false_type{}, q, valid, d, pos, vxn, cand);
+      const int k = st == 0 ? window_slot(s, tile, d) : -1;
+      const bool near = k >= 0;
+      // stable rank inside this wave's unit of the order (from the unit's end backwards
+      // for a backward wave)
+      const unsigned long long m = match_key(k, near, nbits);
+      const int rank = __popcll(m & (kRev ? gt : lt));
+      uint32_t dst = sink;
+      if (near) {
+        if constexpr (kRev) dst = sh.off[wv][k] - 1u - static_cast<uint32_t>(rank);
+        else dst = sh.off[wv][k] + static_cast<uint32_t>(rank);
+      }
+      if (near && rank == 0) {
+        if constexpr (kRev) sh.off[wv][k] = dst + 1u - static_cast<uint32_t>(__popcll(m));
+        else sh.off[wv][k] = dst + static_cast<uint32_t>(__popcll(m));
+      }
+      if (near && dst >= n_out) {
+        atomicOr(&sh.err, kErrState);
+        dst = sink;
+      }
+      store_record<P>(out, dst, d, pos, vxn, q.vy, q.vz, q.id);
+      const bool far = st == 0 && !near;
+      const uint32_t e = list_candidate(rev_tag, cand, far, near ? dst : kNoDest, q, d, pos, vxn);
+      const unsigned long long fm = __ballot(far);
+      if (fm) {
+        if (qn + static_cast<uint32_t>(__popcll(fm)) > static_cast<uint32_t>(kFarQ)) flush();
+        if (far) {
+          const uint32_t j = qn + static_cast<uint32_t>(__popcll(fm & lt));
+          uint32_t* f = sh.fq[wv][j];
+          f[0] = i;
+          f[1] = static_cast<uint32_t>(d);
+          if constexpr (std::is_same<P, P32>::value) {
+            f[2] = __float_as_uint(pos);
+            f[3] = __float_as_uint(vxn);
+            f[4] = __float_as_uint(q.vy);
+            f[5] = __float_as_uint(q.vz);
+          } else {
+            sh.fqd[wv][j][0] = pos;
+            sh.fqd[wv][j][1] = vxn;
+            sh.fqd[wv][j][2] = q.vy;
+            sh.fqd[wv][j][3] = q.vz;
           }
-          store_record<P>(out, dst, d, pos, vxn, q.vy, q.vz, q.id);
-          const bool far = st == 0 && !near;
-          const uint32_t e = list_candidate(cand, far, near ? dst : kNoDest, q, d, pos, vxn);
-          const unsigned long long fm = __ballot(far);
-          if (fm) {
-            if (qn + static_cast<uint32_t>(__popcll(fm)) > static_cast<uint32_t>(kFarQ)) flush();
-            if (far) {
-              const uint32_t j = qn + static_cast<uint32_t>(__popcll(fm & lt));
-              uint32_t* f = sh.fq[wv][j];
-              f[0] = i;
-              f[1] = static_cast<uint32_t>(d);
-              if constexpr (std::is_same<P, P32>::value) {
-                f[2] = __float_as_uint(pos);
-                f[3] = __float_as_uint(vxn);
-                f[4] = __float_as_uint(q.vy);
-                f[5] = __float_as_uint(q.vz);
-              } else {
-                sh.fqd[wv][j][0] = pos;
-                sh.fqd[wv][j][1] = vxn;
-                sh.fqd[wv][j][2] = q.vy;
-                sh.fqd[wv][j][3] = q.vz;
-              }
-              f[6] = q.id;
-              f[7] = cand ? e : kNoDest;
-            }
-            qn += static_cast<uint32_t>(__popcll(fm));
-          }
-          // deposit of the near particles into this wave's window (m groups them by slot)
-          real w0 = real(0), w1 = real(0);
-          if (near) deposit_weights<P>(pos, w0, w1);
-          const unsigned long long lead = __ballot(near && rank == 0);
-          if (__popcll(lead) <= kReduceSlots) {
-            unsigned long long rem = lead;
-            while (rem) {
-              const int L = __ffsll(static_cast<long long>(rem)) - 1;
-              const int key = __shfl(k, L, 64);
-              const bool mine = near && k == key;
-              const real a = wave_sum<real>(mine ? w0 : real(0));
-              const real b = wave_sum<real>(mine ? w1 : real(0));
-              if (lane == L) {
-                sh.dep[wv][key] += a;
-                sh.dep[wv][key + 1] += b;
-              }
-              rem &= rem - 1ull;
-            }
-          } else if (near) {
-            atomicAdd(&sh.dep[wv][k], w0);
-            atomicAdd(&sh.dep[wv][k + 1], w1);
-          }
-        });
+          f[6] = q.id;
+          f[7] = cand ? e : kNoDest;
+        }
+        qn += static_cast<uint32_t>(__popcll(fm));
+      }
+      // deposit of the near particles into this wave's window (LDS float atomics: the
+      // LDS pipe absorbs the same-slot conflicts, the vector ALU stays free)
+      if (near) {
+        real w0, w1;
+        deposit_weights<P>(pos, w0, w1);
+        atomicAdd(&sh.dep[wv][k], w0);
+        atomicAdd(&sh.dep[wv][k + 1], w1);
+      }
+    };
+    if (wave_reversed(r, wv)) {
+      stream_range_rev<Part<P>, MainU<P>::value>(
+          wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
+            cell_body(std::true_type{}, q, i, valid);
+          });
+    } else {
+      stream_range<Part<P>, MainU<P>::value>(
+          wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
+            cell_body(std::false_type{}, q, i, valid);
+          });
+    }
     if (qn) flush();
   } else {
     // Tail tile: rank per cell against this wave's global tail row, one returning atomic
@@ -1057,7 +1196,7 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
             }
           }
           store_record<P>(out, dst == kNoDest ? sink : dst, d, pos, vxn, q.vy, q.vz, q.id);
-          list_candidate(cand, false, dst, q, d, pos, vxn);
+          list_candidate(std::false_type{}, cand, false, dst, q, d, pos, vxn);
           if (dst != kNoDest) far_deposit<P>(s, d, pos);
         });
   }
@@ -1105,8 +1244,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   seg_pre[0] = 0u;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
-    seg_lo[w] = wave_range(r, w).lo;
-    seg_pre[w + 1] = seg_pre[w] + s.cand_cnt[tile * kWaves + w];
+    const WaveRange wr = wave_range(r, w);
+    const uint32_t nc = s.cand_cnt[tile * kWaves + w];
+    seg_lo[w] = wave_reversed(r, w) ? wr.hi - nc : wr.lo;  // see list_candidate in k_main
+    seg_pre[w + 1] = seg_pre[w] + nc;
   }
   const uint32_t n = seg_pre[kWaves];
   if (n == 0u) {
@@ -1122,9 +1263,9 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     births = 0u;
   }
   __syncthreads();
-  const RecPtr out = rec_of(sim.sp[tt.x].fld[pq]);
-  const RecPtr stage_e = rec_of(sim.sp[tt.x].stage[0]);
-  const RecPtr stage_i = rec_of(sim.sp[tt.x].stage[1]);
+  const RecPtr out = rec_buf(&sim.sp[tt.x], pq);
+  const RecPtr stage_e = rec_stage(&sim.sp[tt.x], 0);
+  const RecPtr stage_i = rec_stage(&sim.sp[tt.x], 1);
   const SpeciesDev ion = sim.sp[s.sp == 0 ? tt.x + 1 : tt.x];  // used by electron tiles
   real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (s.W + 1);
   for (uint32_t b = 0; b < n; b += kWG) {
@@ -1138,14 +1279,11 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
 #pragma unroll
       for (int k = 1; k < kWaves; ++k) w += e >= seg_pre[k] ? 1 : 0;
       const uint32_t idx = seg_lo[w] + (e - seg_pre[w]);
-      const uint4 c = idx < s.cap ? s.cand[idx] : make_uint4(kNoDest, 0u, 0u, 0u);
+      real v[3] = {real(0), real(0), real(0)};
+      const uint4 c = idx < s.cap ? cand_load<P>(s.cand, idx, pos, v)
+                                  : make_uint4(kNoDest, 0u, 0u, 0u);
       const uint32_t dst = c.x;
       if (dst != kNoDest && dst < s.cap) {
-        pos = static_cast<const real GM*>(s.cand_f[0])[idx];
-        real v[3];
-        v[0] = static_cast<const real GM*>(s.cand_f[1])[idx];
-        v[1] = static_cast<const real GM*>(s.cand_f[2])[idx];
-        v[2] = static_cast<const real GM*>(s.cand_f[3])[idx];
         if constexpr (std::is_same<P, P32>::value) {
           d = static_cast<int>(c.z);
         } else {
@@ -1155,9 +1293,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
         const int ch = collide<P>(s, c.y, step32, b0.y, b0.z, v, vs, vi);
         if (ch > 0) {
           atomicAdd(&coll[ch - 1], 1u);
-          static_cast<real GM*>(out[F_VX])[dst] = v[0];
-          static_cast<real GM*>(out[F_VY])[dst] = v[1];
-          static_cast<real GM*>(out[F_VZ])[dst] = v[2];
+          const uint32_t o = real_off<P>(out, dst);
+          sto<real>(out.f[F_VX], o, v[0]);
+          sto<real>(out.f[F_VY], o, v[1]);
+          sto<real>(out.f[F_VZ], o, v[2]);
           born = s.sp == 0 && ch == 3;
         }
       }
@@ -1194,28 +1333,27 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   }
 }
 // ====================================================================================
-// k_finalize: one workgroup per (discharge, species).  Births are appended after the
-// sorted survivors in the order of their parents' input index (the electron tiles are
-// in index order and each keeps its births in index order); the children take the next
-// ids of their species.  The last workgroup to finish advances the step counter.
+// Births are appended after the sorted survivors in the order of their parents' input
+// index (the electron tiles are in index order and each keeps its births in index
+// order); the children take the next ids of their species.
+// k_birth_scan (one workgroup per discharge) scans the electron tiles' birth counts and
+// settles how many births fit and their first id; k_finalize (one wave per tile, all
+// tiles) copies each electron tile's staged births -- electrons and ions -- to their
+// places, and its last workgroup advances the step counter.
 // ====================================================================================
-template <class P>
-__global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict__ simp) {
-  using real = typename Part<P>::real;
+__global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev s = sim.sp[blockIdx.x];
-  const SpeciesDev se = sim.sp[blockIdx.x - s.sp];
+  const DischargeDev dd = sim.ds[blockIdx.x];
+  const SpeciesDev se = sim.sp[dd.spec0];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
-  __shared__ uint32_t sh_fit, sh_nid;
-  const unsigned long long step = *sim.step;
-  const int q = static_cast<int>((step + 1ull) & 1ull);
+  const int q = static_cast<int>((*sim.step + 1ull) & 1ull);
   const int nt = se.n_tiles + se.n_tail;
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) s.birth_base[t] = se.birth_cnt[t];
-  __syncthreads();
-  const uint32_t B = array_exclusive_scan(s.birth_base, nt, lds);
-  const uint32_t n_surv = s.n_sorted[q];
-  if (threadIdx.x == 0) {
-    s.birth_base[nt] = B;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) se.birth_base[t] = se.birth_cnt[t];
+  const uint32_t B = array_exclusive_scan(se.birth_base, nt, lds);
+  if (threadIdx.x < 2) {
+    const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
+    if (threadIdx.x == 0) se.birth_base[nt] = B;
+    const uint32_t n_surv = s.n_sorted[q];
     uint32_t fit = B;
     const uint32_t room = s.cap > n_surv ? s.cap - n_surv : 0u;
     if (fit > room) {
@@ -1227,46 +1365,63 @@ __global__ __launch_bounds__(kSolveWG) void k_finalize(const SimDev* __restrict_
       fit = 0xFFFFFFFFu - nid;
       atomicOr(sim.error, kErrIdOverflow);
     }
-    sh_fit = fit;
-    sh_nid = nid;
-  }
-  __syncthreads();
-  const uint32_t fit = sh_fit, nid = sh_nid;
-  const RecPtr src = rec_of(sim.sp[blockIdx.x - s.sp].stage[s.sp]);
-  const RecPtr dst = rec_of(sim.sp[blockIdx.x].fld[q]);
-  for (uint32_t b = threadIdx.x; b < fit; b += blockDim.x) {
-    int lo = 0, hi = nt;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s.birth_base[mid] <= b) lo = mid;
-      else hi = mid;
-    }
-    const uint32_t si = se.tile_first[lo] + (b - s.birth_base[lo]);
-    const uint32_t di = n_surv + b;
-    if (si >= se.cap) continue;
-    int cell = 0;
-    real pos;
-    if constexpr (std::is_same<P, P32>::value) {
-      cell = static_cast<const int GM*>(src[F32_CELL])[si];
-      pos = static_cast<const float GM*>(src[F32_OFF])[si];
-    } else {
-      pos = static_cast<const double GM*>(src[F64_X])[si];
-    }
-    store_record<P>(dst, di, cell, pos, static_cast<const real GM*>(src[F_VX])[si],
-                    static_cast<const real GM*>(src[F_VY])[si],
-                    static_cast<const real GM*>(src[F_VZ])[si], nid + b);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+    s.fin[0] = fit;
+    s.fin[1] = nid;
     *s.psteps += static_cast<unsigned long long>(s.n_total[q ^ 1]);
     s.n_total[q] = n_surv + fit;
     *s.next_id = nid + fit;
     *s.births += fit;
-    __threadfence();
+  }
+}
+
+template <class P>
+__global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ simp) {
+  using real = typename Part<P>::real;
+  const SimDev& sim = *simp;
+  const int lane = threadIdx.x & 63;
+  const int g = blockIdx.x * kWaves + wave_id();
+  const unsigned long long step = *sim.step;
+  const int q = static_cast<int>((step + 1ull) & 1ull);
+  if (g < sim.total_tiles) {
+    const int2 tt = sim.tile_table[g];
+    const SpeciesDev se = sim.sp[tt.x];
+    if (se.sp == 0) {
+      const int t = tt.y;
+      const uint32_t b0 = se.birth_base[t], b1 = se.birth_base[t + 1];
+      const uint32_t first = se.tile_first[t];
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        const SpeciesDev s = sim.sp[tt.x + sp];
+        const uint32_t fit = s.fin[0], nid = s.fin[1];
+        const uint32_t n_surv = s.n_sorted[q];
+        const RecPtr src = rec_stage(&sim.sp[tt.x], sp);
+        const RecPtr dst = rec_buf(&sim.sp[tt.x + sp], q);
+        const uint32_t end = min(b1, fit);
+        for (uint32_t b = b0 + static_cast<uint32_t>(lane); b < end; b += 64u) {
+          const uint32_t si = first + (b - b0);
+          if (si >= se.cap) continue;
+          int cell = 0;
+          real pos;
+          if constexpr (std::is_same<P, P32>::value) {
+            cell = ldg<int>(src.f[F32_CELL], si);
+            pos = ldg<float>(src.f[F32_OFF], si);
+          } else {
+            pos = ldg<double>(src.f[F64_X], si);
+          }
+          store_record<P>(dst, n_surv + b, cell, pos, ldg<real>(src.f[F_VX], si),
+                          ldg<real>(src.f[F_VY], si), ldg<real>(src.f[F_VZ], si), nid + b);
+        }
+      }
+    }
+  }
+  // The last workgroup to finish advances the step; the kernel boundary makes the new
+  // value visible to the next kernels (no fence: on this GPU a device-scope fence writes
+  // back the whole L2).
+  __syncthreads();
+  if (threadIdx.x == 0) {
     const uint32_t done = atomicAdd(sim.fin_count, 1u);
-    if (done == static_cast<uint32_t>(sim.n_spec) - 1u) {
+    if (done == gridDim.x - 1u) {
       *sim.fin_count = 0u;
-      __threadfence();
       *sim.step = step + 1ull;
     }
   }
@@ -1323,8 +1478,11 @@ void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hip
 
 void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                      hipEvent_t e1) {
-  if (li.fp32) launch(k_finalize<P32>, dim3(li.n_spec), dim3(kSolveWG), st, e0, e1, sim);
-  else launch(k_finalize<P64>, dim3(li.n_spec), dim3(kSolveWG), st, e0, e1, sim);
+  launch(k_birth_scan, dim3(li.n_ds), dim3(kSolveWG), st, e0, static_cast<hipEvent_t>(nullptr),
+         sim);
+  const dim3 grid((li.total_tiles + kWaves - 1) / kWaves);
+  if (li.fp32) launch(k_finalize<P32>, grid, dim3(kWG), st, static_cast<hipEvent_t>(nullptr), e1, sim);
+  else launch(k_finalize<P64>, grid, dim3(kWG), st, static_cast<hipEvent_t>(nullptr), e1, sim);
 }
 
 }  // namespace fspic

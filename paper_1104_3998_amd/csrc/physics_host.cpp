@@ -82,8 +82,10 @@ int validate_config(const pic_config& c, std::string* why) {
   if (c.periodic && c.n_cells < 3) return bad("periodic box needs >= 3 cells");
   if (c.n_e0 < 1) return bad("n_e0 must be >= 1 (it sets the macro-particle weight)");
   if (c.capacity_e < c.n_e0 || c.capacity_i < c.n_i0) return bad("capacity below n0");
-  if (c.capacity_e >= 0x7FFFFFFFull || c.capacity_i >= 0x7FFFFFFFull)
-    return bad("capacity must be < 2^31 - 1");
+  // the kernels address an array element by a 32-bit byte offset: both buffers of an
+  // 8-byte field, or the candidate records (48 bytes in FP64), must stay below 4 GiB
+  if (c.capacity_e >= (1ull << 26) || c.capacity_i >= (1ull << 26))
+    return bad("capacity must be < 2^26 per species");
   if (!(c.length_m > 0) || !(c.dt_s > 0) || !(c.n0_m3 > 0) || !(c.mass_i_amu > 0))
     return bad("length, dt, n0 and ion mass must be positive");
   if (!(c.te_ev >= 0) || !(c.ti_ev >= 0) || !(c.gas_pa >= 0) || !(c.gas_k > 0))

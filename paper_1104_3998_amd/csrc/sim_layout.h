@@ -59,6 +59,7 @@ struct SpeciesDev {
   // particle arrays: [buffer][field]; FP32 cell+offset: cell, off, vx, vy, vz, id;
   // FP64: x, (unused), vx, vy, vz, id
   void GM* fld[2][6];
+  uint32_t bstride4, bstride8;  // fld[1][f] - fld[0][f] in bytes for 4- and 8-byte fields
   // birth staging (electron species only): [0] secondary electrons, [1] new ions;
   // fields as in fld
   void GM* stage[2][6];
@@ -82,13 +83,15 @@ struct SpeciesDev {
   uint32_t GM* far_base;       // [n_cells]
   uint32_t GM* base;           // [n_cells] first output index of each cell
   uint32_t GM* far_dest;       // [cap] output index of each far mover, by input index
-  uint4 GM* cand;              // [cap] MCC candidates: (output slot, id, cell, 0), stored in the
-                            // input-index range of the wave that found them, in input order
-  void GM* cand_f[4];          // [cap] each: post-push position word, vx, vy, vz of a candidate
+  void GM* cand;               // [cap + 1] MCC candidate records (output slot, id, cell and the
+                               // post-push position and velocity; 32 B in FP32, 48 B in FP64),
+                               // stored in the input-index range of the wave that found them
   uint32_t GM* cand_cnt;       // [(n_tiles + n_tail) * kWaves] candidates per (tile, wave)
   uint32_t GM* birth_cnt;      // [n_tiles + n_tail] births of each electron tile
   uint32_t GM* tile_first;     // [n_tiles + n_tail] first input index of each tile
   uint32_t GM* birth_base;     // [n_tiles + n_tail + 1] exclusive scan of the electron births
+                               // (electron species only)
+  uint32_t GM* fin;            // [2] births that fit this step, id of the first
   unsigned long long GM* absorbed;   // [2] per wall (0 left, 1 right)
   double GM* absorbed_energy;        // [2] eV
   unsigned long long GM* births;     // [1]
