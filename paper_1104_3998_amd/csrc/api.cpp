@@ -51,24 +51,14 @@ struct Plan {
   size_t bytes = 0;
 };
 
-// Workgroup -> tile table of the particle kernels.  Workgroups are handed to the 8 XCDs
-// in turn (workgroup b to XCD b mod 8), and each XCD has its own L2; the table gives
-// each XCD one contiguous run of the tile list, so neighbouring tiles -- whose outputs
-// share cache lines at the cell boundaries -- are written through the same L2.  The
-// (small) tail tiles go first so that they start early.
-std::vector<int2> xcd_order(const std::vector<int2>& tail, const std::vector<int2>& cells) {
-  constexpr int kXcds = 8;
+// Workgroup -> tile table of the particle kernels: the (small) tail tiles first, so that
+// they start early, then the cell tiles in order.  (Giving each XCD one contiguous run of
+// tiles was measured slower for k_main: the particle density, and with it the work per
+// tile, varies along the discharge, and contiguous runs load the XCDs unevenly.)
+std::vector<int2> tile_order(const std::vector<int2>& tail, const std::vector<int2>& cells) {
   std::vector<int2> list(tail);
   list.insert(list.end(), cells.begin(), cells.end());
-  const size_t n = list.size();
-  std::vector<int2> table(n);
-  size_t start = 0;
-  for (int x = 0; x < kXcds; ++x) {
-    const size_t count = n > static_cast<size_t>(x) ? (n - x + kXcds - 1) / kXcds : 0;
-    for (size_t m = 0; m < count; ++m) table[m * kXcds + x] = list[start + m];
-    start += count;
-  }
-  return table;
+  return list;
 }
 
 int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* why) {
@@ -234,7 +224,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       for (int j = 0; j < tc.n_tail; ++j) tail_tiles.push_back(make_int2(2 * d + s, tc.n_tiles + j));
     }
   }
-  pl->tile_table = xcd_order(tail_tiles, cell_tiles);
+  pl->tile_table = tile_order(tail_tiles, cell_tiles);
   const int n_gtiles = 256;
   for (int i = 0; i < 2 * n; ++i)
     pl->sp[i].gsort_hist = cv.take<uint32_t>(static_cast<size_t>(n_gtiles) * pl->sp[i].n_cells);
@@ -245,6 +235,9 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   pl->sim.n_spec = 2 * n;
   pl->sim.total_tiles = static_cast<int>(pl->tile_table.size());
   pl->sim.max_nodes = max_nodes;
+  int max_window = 1;
+  for (const SpeciesDev& S : pl->sp) max_window = std::max(max_window, static_cast<int>(S.W));
+  pl->sim.max_window = max_window;
   pl->d_ds = cv.take<DischargeDev>(n);
   pl->d_sp = cv.take<SpeciesDev>(2 * n);
   pl->d_tt = cv.take<int2>(pl->tile_table.size());
@@ -261,6 +254,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   li.max_cap = max_cap;
   li.n_gtiles = n_gtiles;
   li.max_cells = max_cells;
+  li.max_window = max_window;
   li.fp32 = fp32;
   return PIC_OK;
 }

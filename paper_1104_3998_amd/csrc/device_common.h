@@ -55,8 +55,10 @@ __device__ __forceinline__ void normals64(uint4 b, double& z0, double& z1) {
   const double ub = u53(b.z, b.w);
   const double r = sqrt(-2.0 * log(1.0 - ua));
   const double th = kTwoPi * ub;
-  z0 = r * cos(th);
-  z1 = r * sin(th);
+  double sn, cs;
+  sincos(th, &sn, &cs);  // one argument reduction for both
+  z0 = r * cs;
+  z1 = r * sn;
 }
 
 // isotropic unit vector, first component along the discharge axis
@@ -66,9 +68,11 @@ __device__ __forceinline__ void direction64(uint4 b, double& n0, double& n1, dou
   const double ct = 1.0 - 2.0 * ua;
   const double st = sqrt(1.0 - ct * ct);
   const double ph = kTwoPi * ub;
+  double sn, cs;
+  sincos(ph, &sn, &cs);
   n0 = ct;
-  n1 = st * cos(ph);
-  n2 = st * sin(ph);
+  n1 = st * cs;
+  n2 = st * sn;
 }
 
 __device__ __forceinline__ void direction32(uint4 b, float& n0, float& n1, float& n2) {

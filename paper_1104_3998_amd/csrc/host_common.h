@@ -21,7 +21,7 @@ double ion_mass(const pic_config& c);
 
 // Launch geometry the host needs beside the device descriptors.
 struct LaunchInfo {
-  int n_ds, n_spec, total_tiles, max_nodes, max_cap, n_gtiles, max_cells;
+  int n_ds, n_spec, total_tiles, max_nodes, max_cap, n_gtiles, max_cells, max_window;
   bool fp32;
 };
 

@@ -452,105 +452,107 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
   const SimDev& sim = *simp;
   const DischargeDev dd = sim.ds[blockIdx.x];
   __shared__ double lds_d[kSolveWG / 64 + 1];
+  __shared__ double sv[kMaxCells + 1];  // rho_j, then R_j, then the slope s_j
   const unsigned long long step = init_mode ? 0ull : *sim.step;
   const int N = dd.n_cells;
   const int nn = dd.n_nodes;
   const double GM* we = dd.w[0];
   const double GM* wi = dd.w[1];
-  double GM* phi = dd.phi;  // holds R_j, then Phi
-  double* E = dd.E64;    // holds s_j, then E
-  const int per = (N + blockDim.x - 1) / blockDim.x;
-  const int lo = threadIdx.x * per;
-  const int hi = min(lo + per, N);
+  const int tid = threadIdx.x;
+  // thread tid owns the nodes [lo, hi); the node values stay in LDS through the solve
+  const int per = (nn + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+  const int lo = tid * per;
+  const int hi = min(lo + per, nn);
+  for (int j = lo; j < hi; ++j) sv[j] = wi[j] - we[j];
+  const double rho_wall0 = wi[0] - we[0];
+  const double rho_wallN = dd.periodic ? 0.0 : wi[N] - we[N];
+  const int hc = min(hi, N);  // the thread's cells
   double total;
   // mean charge (periodic only)
   double mean = 0.0;
   if (dd.periodic) {
     double part = 0.0;
-    for (int j = lo; j < hi; ++j) part += wi[j] - we[j];
+    for (int j = lo; j < hc; ++j) part += sv[j];
     block_exclusive_scan(part, lds_d, total);
     mean = total / static_cast<double>(N);
   }
   // R_j = sum_{k=1..j} (rho_k - mean), j = 0..N-1
   {
     double part = 0.0;
-    for (int j = lo; j < hi; ++j)
-      if (j >= 1) part += (wi[j] - we[j]) - mean;
+    for (int j = max(lo, 1); j < hc; ++j) part += sv[j] - mean;
     double run = block_exclusive_scan(part, lds_d, total);
-    for (int j = lo; j < hi; ++j) {
-      if (j >= 1) run += (wi[j] - we[j]) - mean;
-      phi[j] = run;
+    for (int j = lo; j < hc; ++j) {
+      if (j >= 1) run += sv[j] - mean;
+      sv[j] = run;
     }
   }
-  __syncthreads();
   double sum_r;
   {
     double part = 0.0;
-    for (int j = lo; j < hi; ++j) part += phi[j];
+    for (int j = lo; j < hc; ++j) part += sv[j];
     block_exclusive_scan(part, lds_d, sum_r);
   }
   const double a = dd.periodic ? 0.0 : dd.vhat_amp * sin(dd.phase_per_step * static_cast<double>(step));
   const double s0 = (0.0 - a + sum_r) / static_cast<double>(N);
-  // s_j and Phi_j = a + sum_{m<j} s_m
+  // s_j = s0 - R_j and Phi_j = a + sum_{m<j} s_m
+  double GM* phi = dd.phi;
   {
     double part = 0.0;
-    for (int j = lo; j < hi; ++j) part += s0 - phi[j];
-    __syncthreads();
+    for (int j = lo; j < hc; ++j) part += s0 - sv[j];
     double run = block_exclusive_scan(part, lds_d, total) + a;
-    for (int j = lo; j < hi; ++j) {
-      const double sj = s0 - phi[j];
-      E[j] = sj;
+    for (int j = lo; j < hc; ++j) {
+      const double sj = s0 - sv[j];
+      sv[j] = sj;
       phi[j] = run;
       run += sj;
     }
   }
+  if (!dd.periodic && tid == 0) phi[N] = 0.0;
   __syncthreads();
-  if (!dd.periodic && threadIdx.x == 0) phi[N] = 0.0;
-  // E from the slopes (E[j] holds s_j for j < N)
-  double GM* tmp = dd.scratch;
-  for (int j = threadIdx.x; j < N; j += blockDim.x) tmp[j] = E[j];
-  __syncthreads();
-  for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+  // E from the slopes
+  for (int j = lo; j < hi; ++j) {
     double e;
     if (dd.periodic) {
       const int jm = j == 0 ? N - 1 : j - 1;
-      e = -(tmp[jm] + tmp[j]) / 2.0;
+      e = -(sv[jm] + sv[j]) / 2.0;
     } else if (j == 0) {
-      e = -tmp[0] - (wi[0] - we[0]);
+      e = -sv[0] - rho_wall0;
     } else if (j == N) {
-      e = -tmp[N - 1] + (wi[N] - we[N]);
+      e = -sv[N - 1] + rho_wallN;
     } else {
-      e = -(tmp[j - 1] + tmp[j]) / 2.0;
+      e = -(sv[j - 1] + sv[j]) / 2.0;
     }
-    E[j] = e;
+    dd.E64[j] = e;
     dd.E32[j] = static_cast<float>(e);
   }
-  __syncthreads();
   if (!init_mode && static_cast<long long>(step) >= dd.avg_start) {
-    for (int j = threadIdx.x; j < nn; j += blockDim.x) {
+    for (int j = tid; j < nn; j += blockDim.x) {
       dd.acc_w[0][j] += we[j];
       dd.acc_w[1][j] += wi[j];
       dd.acc_phi[j] += phi[j];
     }
-    if (threadIdx.x == 0) *dd.acc_count += 1ull;
+    if (tid == 0) *dd.acc_count += 1ull;
   }
-  if (!init_mode && threadIdx.x == 0 && diag_step(dd, step)) *dd.eedf_samples += 1ull;
+  if (!init_mode && tid == 0 && diag_step(dd, step)) *dd.eedf_samples += 1ull;
   // per-step far-mover state of both species starts empty
   for (int sp = 0; sp < 2; ++sp) {
     const SpeciesDev s = sim.sp[dd.spec0 + sp];
-    for (int j = threadIdx.x; j < nn; j += blockDim.x) s.far_w[j] = 0.0;
-    for (int c = threadIdx.x; c < N; c += blockDim.x) s.far_cell_cnt[c] = 0u;
-    if (threadIdx.x == 0) *s.far_count = 0u;
+    for (int j = tid; j < nn; j += blockDim.x) s.far_w[j] = 0.0;
+    for (int c = tid; c < N; c += blockDim.x) s.far_cell_cnt[c] = 0u;
+    if (tid == 0) *s.far_count = 0u;
   }
 }
 
 // ====================================================================================
 // k_hist: post-push cell histogram (sort pre-pass).  Each wave counts its own piece of
-// the tile into its own LDS row over the tile's window: lanes with the same slot are
-// grouped with ballots and one leader adds the group's count.  Particles that leave the
-// window go to the far list.  A tail tile (the unsorted births at the end of the array)
+// the tile into its own LDS histogram over the tile's window with LDS atomic increments,
+// spread over lane-indexed copies (a chunk of 64 particles comes from one cell and lands
+// in a few slots; with one copy the increments would queue on those slots).  Particles
+// that leave the window go to the far list.  A tail tile (the unsorted births at the end of the array)
 // has no window: each of its waves counts into its own global row over all cells.
 // ====================================================================================
+constexpr int kHistCopies = 8;
+
 template <class P>
 struct HistU;
 template <>
@@ -572,16 +574,20 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   const int p = static_cast<int>(*sim.step & 1ull);
   const TileRange r = tile_range(s, tt.y, p);
   __shared__ real Elds[kMaxCellsPerTile + 1];
-  __shared__ uint32_t h[kWaves][kMaxWindow];
   __shared__ uint32_t hq[kWaves][64][2];
+  // per-wave histograms, kHistCopies copies each (lane l counts into copy l mod
+  // kHistCopies, so an LDS atomic has few lanes on one slot); W_max slots per copy
+  extern __shared__ uint32_t hdyn[];
   const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const unsigned long long lt = lanes_below();
   const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
                                                   : reinterpret_cast<const real GM*>(dd.E64);
   load_field_window<real>(s, E, r, Elds);
   const int W = s.W;
-  for (int k = tid; k < kWaves * W; k += kWG) h[k / W][k % W] = 0u;
-  const int nbits = key_bits(W);
+  const int Wm = sim.max_window;
+  for (int k = tid; k < kWaves * kHistCopies * Wm; k += kWG) hdyn[k] = 0u;
+  uint32_t* h = hdyn + wv * kHistCopies * Wm;
+  uint32_t* hl = h + (lane & (kHistCopies - 1)) * Wm;
   __syncthreads();
   const WaveRange wr = wave_range(r, wv);
   const RecPtr in = rec_buf(&sim.sp[tt.x], p);
@@ -612,8 +618,7 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
           if (valid) st = push_particle<P, false>(s, dd, Elds, r, q, d, pos, vxn);
           const int k = st == 0 ? window_slot(s, tt.y, d) : -1;
           const bool near = k >= 0;
-          const unsigned long long m = match_key(k, near, nbits);
-          if (near && __popcll(m & lt) == 0) h[wv][k] += static_cast<uint32_t>(__popcll(m));
+          if (near) atomicAdd(&hl[k], 1u);
           const bool far = st == 0 && !near;
           const unsigned long long fm = __ballot(far);
           if (fm) {
@@ -628,7 +633,12 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
         });
     if (qn) flush();
     uint32_t GM* row = s.hist + (static_cast<size_t>(tt.y) * kWaves + wv) * W;
-    for (int k = lane; k < W; k += 64) row[k] = h[wv][k];
+    for (int k = lane; k < W; k += 64) {  // the wave's own copies: no barrier needed
+      uint32_t n = 0u;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c) n += h[c * Wm + k];
+      row[k] = n;
+    }
   } else {
     uint32_t GM* row = s.thist +
                     static_cast<size_t>((tt.y - s.n_tiles) * kWaves + wv) * s.n_cells;
@@ -676,34 +686,54 @@ __global__ __launch_bounds__(256) void k_scan_cells(const SimDev* __restrict__ s
   const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
   const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
   const int units = (n0 + n1) * kWaves;
-  uint32_t run = 0;
-  for (int u0 = 0; u0 < units; u0 += 64) {
-    const int u = u0 + lane;
-    uint32_t v = 0u;
-    size_t o = 0;
-    if (u < units) {
-      const int ti = u / kWaves, w = u - ti * kWaves;
-      const int t = ti < n0 ? a[0] + ti : a[1] + (ti - n0);
-      o = (static_cast<size_t>(t) * kWaves + w) * W + covering_slot(s, c, t);
-      v = s.hist[o];
-    }
-    const uint32_t inc = wave_inclusive_scan(v);
-    if (u < units) s.tilerel[o] = run + inc - v;
-    run += __shfl(inc, 63, 64);
-  }
-  run += s.far_cell_cnt[c];
   const int rows = s.n_tail * kWaves;
-  for (int j0 = 0; j0 < rows; j0 += 64) {
-    const int jj = j0 + lane;
-    uint32_t v = 0u;
-    const size_t o = static_cast<size_t>(jj) * N + c;
-    if (jj < rows) v = s.thist[o];
-    const uint32_t inc = wave_inclusive_scan(v);
-    if (jj < rows) {
-      s.trel[o] = run + inc - v;
-      s.thist[o] = 0u;
+  // Loads of up to kB passes are issued together, then scanned: one memory round trip
+  // for the usual cell (at most 64 kB units and tail rows).
+  constexpr int kB = 4;
+  uint32_t run = 0;
+  const uint32_t nfar = s.far_cell_cnt[c];
+  for (int u0 = 0; u0 < units; u0 += 64 * kB) {
+    uint32_t v[kB];
+    size_t o[kB];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int u = u0 + q * 64 + lane;
+      v[q] = 0u;
+      o[q] = 0;
+      if (u < units) {
+        const int ti = u / kWaves, w = u - ti * kWaves;
+        const int t = ti < n0 ? a[0] + ti : a[1] + (ti - n0);
+        o[q] = (static_cast<size_t>(t) * kWaves + w) * W + covering_slot(s, c, t);
+        v[q] = s.hist[o[q]];
+      }
     }
-    run += __shfl(inc, 63, 64);
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int u = u0 + q * 64 + lane;
+      const uint32_t inc = wave_inclusive_scan(v[q]);
+      if (u < units) s.tilerel[o[q]] = run + inc - v[q];
+      run += __shfl(inc, 63, 64);
+    }
+  }
+  run += nfar;
+  for (int j0 = 0; j0 < rows; j0 += 64 * kB) {
+    uint32_t v[kB];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int jj = j0 + q * 64 + lane;
+      v[q] = jj < rows ? s.thist[static_cast<size_t>(jj) * N + c] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int jj = j0 + q * 64 + lane;
+      const uint32_t inc = wave_inclusive_scan(v[q]);
+      if (jj < rows) {
+        const size_t o = static_cast<size_t>(jj) * N + c;
+        s.trel[o] = run + inc - v[q];
+        s.thist[o] = 0u;
+      }
+      run += __shfl(inc, 63, 64);
+    }
   }
   if (lane == 0) s.base[c] = run;
 }
@@ -787,12 +817,20 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
 constexpr uint32_t kNoDest = 0xFFFFFFFFu;
 constexpr int kFarQ = 64;           // per-wave queue of far movers (one chunk always fits)
 
+template <class real>
+struct DepCopies {
+  static constexpr int value = sizeof(real) == 4 ? 8 : 4;
+};
+
 template <class P>
 struct MainShared {
   using real = typename Part<P>::real;
   real Elds[kMaxCellsPerTile + 1];
   uint32_t off[kWaves][kMaxWindow];  // next output index of each (wave, window slot)
-  real dep[kWaves][kMaxWindow + 1];  // per-wave deposit windows
+  // deposit window in kDepCopies copies shared by the waves; lane l adds into copy
+  // l mod kDepCopies, so one atomic instruction has few lanes on any one address (the
+  // 64 particles of a chunk come from one cell and land in a handful of slots)
+  real dep[DepCopies<real>::value][kMaxWindow + 1];
   uint32_t eedf[kMaxEedfBins + 1];
   uint32_t abs_cnt[2];
   double abs_e[2];
@@ -993,7 +1031,8 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
                           : 0u;
     }
   }
-  for (int k = tid; k < kWaves * (W + 1); k += kWG) sh.dep[k / (W + 1)][k % (W + 1)] = real(0);
+  constexpr int kCopies = DepCopies<real>::value;
+  for (int k = tid; k < kCopies * (W + 1); k += kWG) sh.dep[k / (W + 1)][k % (W + 1)] = real(0);
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG) sh.eedf[k] = 0u;
   if (tid == 0) {
@@ -1153,8 +1192,9 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       if (near) {
         real w0, w1;
         deposit_weights<P>(pos, w0, w1);
-        atomicAdd(&sh.dep[wv][k], w0);
-        atomicAdd(&sh.dep[wv][k + 1], w1);
+        real* dep = sh.dep[lane & (kCopies - 1)];
+        atomicAdd(&dep[k], w0);
+        atomicAdd(&dep[k + 1], w1);
       }
     };
     if (wave_reversed(r, wv)) {
@@ -1205,7 +1245,12 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   // tile epilogue
   if (!r.tail) {
     real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (W + 1);
-    for (int k = tid; k <= W; k += kWG) part[k] = sh.dep[0][k] + sh.dep[1][k] + sh.dep[2][k] + sh.dep[3][k];
+    for (int k = tid; k <= W; k += kWG) {
+      real sum = sh.dep[0][k];
+#pragma unroll
+      for (int c = 1; c < kCopies; ++c) sum += sh.dep[c][k];
+      part[k] = sum;
+    }
   }
   if (tid == 0) {
     s.tile_first[tile] = r.lo;
@@ -1336,10 +1381,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
 // Births are appended after the sorted survivors in the order of their parents' input
 // index (the electron tiles are in index order and each keeps its births in index
 // order); the children take the next ids of their species.
-// k_birth_scan (one workgroup per discharge) scans the electron tiles' birth counts and
-// settles how many births fit and their first id; k_finalize (one wave per tile, all
-// tiles) copies each electron tile's staged births -- electrons and ions -- to their
-// places, and its last workgroup advances the step counter.
+// k_birth_scan (one workgroup per discharge) scans the electron tiles' birth counts,
+// settles how many births fit and their first id, and advances the step counter;
+// k_finalize (one wave per tile, all tiles) copies each electron tile's staged births --
+// electrons and ions -- to their places.
 // ====================================================================================
 __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
@@ -1372,6 +1417,16 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     *s.next_id = nid + fit;
     *s.births += fit;
   }
+  // The last discharge's workgroup advances the step counter (every workgroup read it at
+  // its start); the kernel boundary publishes it to k_finalize and the next step.
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t done = atomicAdd(sim.fin_count, 1u);
+    if (done == gridDim.x - 1u) {
+      *sim.fin_count = 0u;
+      *sim.step = *sim.step + 1ull;
+    }
+  }
 }
 
 template <class P>
@@ -1380,8 +1435,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
   const SimDev& sim = *simp;
   const int lane = threadIdx.x & 63;
   const int g = blockIdx.x * kWaves + wave_id();
-  const unsigned long long step = *sim.step;
-  const int q = static_cast<int>((step + 1ull) & 1ull);
+  const int q = static_cast<int>(*sim.step & 1ull);  // k_birth_scan advanced the step
   if (g < sim.total_tiles) {
     const int2 tt = sim.tile_table[g];
     const SpeciesDev se = sim.sp[tt.x];
@@ -1414,17 +1468,6 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
       }
     }
   }
-  // The last workgroup to finish advances the step; the kernel boundary makes the new
-  // value visible to the next kernels (no fence: on this GPU a device-scope fence writes
-  // back the whole L2).
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t done = atomicAdd(sim.fin_count, 1u);
-    if (done == gridDim.x - 1u) {
-      *sim.fin_count = 0u;
-      *sim.step = step + 1ull;
-    }
-  }
 }
 
 // ====================================================================================
@@ -1432,10 +1475,16 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
 // records them around the kernel's own execution (used for per-kernel timing).
 // ====================================================================================
 template <typename K, typename... Args>
+static void launch_lds(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                       hipEvent_t e0, hipEvent_t e1, Args... args) {
+  if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, lds, st, e0, e1, 0, args...);
+  else kernel<<<grid, block, lds, st>>>(args...);
+}
+
+template <typename K, typename... Args>
 static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0,
                    hipEvent_t e1, Args... args) {
-  if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
-  else kernel<<<grid, block, 0, st>>>(args...);
+  launch_lds(kernel, grid, block, 0, st, e0, e1, args...);
 }
 
 void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
@@ -1452,8 +1501,9 @@ void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStr
 
 void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
-  if (li.fp32) launch(k_hist<P32>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
-  else launch(k_hist<P64>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+  const size_t lds = sizeof(uint32_t) * kWaves * kHistCopies * li.max_window;
+  if (li.fp32) launch_lds(k_hist<P32>, dim3(li.total_tiles), dim3(kWG), lds, st, e0, e1, sim);
+  else launch_lds(k_hist<P64>, dim3(li.total_tiles), dim3(kWG), lds, st, e0, e1, sim);
 }
 
 void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,

@@ -136,6 +136,7 @@ struct SimDev {
   uint32_t GM* error;
   uint32_t GM* fin_count;       // workgroups of the finalize kernel done this step
   int32_t n_ds, n_spec, total_tiles, max_nodes;
+  int32_t max_window;        // largest histogram window W of all species
   const DischargeDev CM* ds;
   const SpeciesDev CM* sp;
   const int2 CM* tile_table;  // workgroup -> (species index, local tile)

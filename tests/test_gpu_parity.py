@@ -122,12 +122,25 @@ def compare_fp32(sim, orc, st_in, label, gbase=None, obase=None, coll_slack=0, d
         g = delta(g, gbase)
     if obase is not None:
         o = delta(o, obase)
+    # With coll_slack > 0, up to coll_slack collision decisions may differ from the
+    # oracle's (the FP32 field rounds differently, and a candidate close to a channel
+    # boundary can flip): those particles' velocities, a flipped ionisation's pair of
+    # births, and their deposits are allowed to differ; everything else must match.
     for s in (0, 1):
         a, po, inp = st[s], orc.particles(s), st_in[s]
         n = a["n"]
-        assert n == orc.count(s), (label, s, "count")
-        ig, io = np.argsort(a["id"]), np.argsort(po["id"])
-        assert np.array_equal(a["id"][ig], po["id"][io]), (label, s, "id sets")
+        assert abs(n - orc.count(s)) <= coll_slack, (label, s, "count")
+        common = np.intersect1d(a["id"], po["id"])
+        assert a["id"].size - common.size <= coll_slack, (label, s, "id sets")
+        assert po["id"].size - common.size <= coll_slack, (label, s, "id sets")
+        if coll_slack:
+            # a flipped ionisation shifts the ids of the later births: compare the
+            # particles that existed before the step one by one, the births by count
+            common = common[common < st_in["next_id"][s]]
+        ig = np.flatnonzero(np.isin(a["id"], common))
+        io = np.flatnonzero(np.isin(po["id"], common))
+        ig = ig[np.argsort(a["id"][ig])]
+        io = io[np.argsort(po["id"][io])]
         xg, xo = positions(a, True)[ig], po["x"][io]
         cg, co = a["cell"][ig].astype(np.int64), np.floor(xo).astype(np.int64)
         fo = xo - co
@@ -138,7 +151,8 @@ def compare_fp32(sim, orc, st_in, label, gbase=None, obase=None, coll_slack=0, d
         vg = velocities(a, True)[:, ig]
         vo = np.stack([po["vx"], po["vy"], po["vz"]])[:, io]
         scale = np.max(np.abs(vo), initial=1e-30)
-        assert np.max(np.abs(vg - vo), initial=0) <= 1e-5 * scale, (label, s, "v")
+        off = np.any(np.abs(vg - vo) > 1e-5 * scale, axis=0)
+        assert int(off.sum()) <= coll_slack, (label, s, "v", int(off.sum()))
         # the GPU's order is the stable sort of the input order by the GPU's own cells
         ns = a["n_sorted"]
         surv = a["id"][:ns]
@@ -152,7 +166,9 @@ def compare_fp32(sim, orc, st_in, label, gbase=None, obase=None, coll_slack=0, d
         first = st_in["next_id"][s]
         assert np.array_equal(born, np.arange(first, first + born.size)), (label, s, "birth ids")
         wo = orc.grid("w_e" if s == 0 else "w_i")
-        assert np.max(np.abs(a["w"] - wo)) <= 1e-5 * max(wo.max(), 1.0), (label, s, "w")
+        # a particle deposits a total weight of 1 (normalised units)
+        assert np.max(np.abs(a["w"] - wo)) <= 1e-5 * max(wo.max(), 1.0) + coll_slack, \
+            (label, s, "w")
         assert g[s]["absorbed"] == o[s]["absorbed"], (label, s, "absorbed")
         for c in range(3):
             assert abs(g[s]["coll"][c] - o[s]["coll"][c]) <= coll_slack, (label, s, "collisions")
