@@ -81,7 +81,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       return PIC_ERR_ARG;
     }
     derive(cfgs[d], &pl->der[d]);
-    choose_tiles(cfgs[d], &pl->tiles[2 * d]);
+    choose_tiles(cfgs[d], pl->der[d], &pl->tiles[2 * d]);
   }
   const bool fp32 = cfgs[0].precision == PIC_FP32_OFFSET;
   const size_t rs = fp32 ? 4 : 8;  // bytes of a real

@@ -15,7 +15,7 @@ struct TileChoice {
 
 int validate_config(const pic_config& c, std::string* why);
 int derive(const pic_config& c, pic_derived* k);
-void choose_tiles(const pic_config& c, TileChoice tc[2]);
+void choose_tiles(const pic_config& c, const pic_derived& k, TileChoice tc[2]);
 double electron_mass();
 double ion_mass(const pic_config& c);
 

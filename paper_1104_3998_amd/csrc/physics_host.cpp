@@ -127,7 +127,7 @@ int derive(const pic_config& c, pic_derived* k) {
   k->vhat_amp = c.v0_volt / k->phi_scale;
   k->drive_phase_per_step = kTwoPiH * c.freq_hz * c.dt_s;
   TileChoice tc[2];
-  choose_tiles(c, tc);
+  choose_tiles(c, *k, tc);
   for (int s = 0; s < 2; ++s) {
     k->cells_per_tile[s] = static_cast<uint32_t>(tc[s].C);
     k->window[s] = static_cast<uint32_t>(tc[s].D);
@@ -138,7 +138,13 @@ int derive(const pic_config& c, pic_derived* k) {
 // Tile geometry.  A workgroup owns C consecutive cells (the paper's "one thread block
 // per sorting cell", Sec. 3.2, with C cells per block instead of one) and sorts the
 // particles that stay within D cells of them; the rest take the far-mover path.
-void choose_tiles(const pic_config& c, TileChoice tc[2]) {
+// Default sizes (measured on the large discharge and the batched scan): an electron tile
+// holds about 2e3 null-collision candidates (P0 of its particles), between 2.5e3 and 2e4
+// particles, so that the MCC pass amortises its per-tile work over enough candidates
+// without making a few very long workgroups; an ion tile holds about 2.5e3 particles (ions
+// have few candidates), and their many short workgroups fill the gaps around the long
+// electron ones in the particle pass.
+void choose_tiles(const pic_config& c, const pic_derived& k, TileChoice tc[2]) {
   const int N = static_cast<int>(c.n_cells);
   const uint64_t n0[2] = {c.n_e0, c.n_i0};
   const int d_default[2] = {32, 4};
@@ -147,17 +153,21 @@ void choose_tiles(const pic_config& c, TileChoice tc[2]) {
     if (c.cells_per_tile[s] > 0) {
       C = static_cast<int>(c.cells_per_tile[s]);
     } else {
+      const double target =
+          s == 0 ? std::min(2.0e4, std::max(2.5e3, 2.0e3 / std::max(k.p0[0], 1e-9))) : 2.5e3;
       const double ppc = std::max(1.0, static_cast<double>(n0[s]) / N);
-      C = static_cast<int>(std::lround(4096.0 / ppc));
+      C = static_cast<int>(std::lround(target / ppc));
     }
     C = std::max(1, std::min(C, std::min(64, N)));
     int D = c.window[s] > 0 ? static_cast<int>(c.window[s]) : d_default[s];
     if (c.periodic) {
+      // C divides N, and the tile with its window (C + 2D cells) leaves at least C + 1
+      // other cells, so no window wraps onto its own tile
       for (;;) {
         C = largest_divisor_at_most(N, C);
-        const int dmax = (N - 2 * C - 1) / 2;
-        if (dmax >= 0 || C == 1) {
-          D = std::max(0, std::min(D, dmax));
+        const int room = N - 2 * C - 1;
+        if (room >= 0 || C == 1) {
+          D = std::max(0, std::min(D, room / 2));
           break;
         }
         C = C - 1;
