@@ -336,6 +336,24 @@ __device__ __forceinline__ unsigned long long match_key(int key, bool act, int n
   return m;
 }
 
+// The same mask, one pass per distinct key among the active lanes: cheaper when a wave's
+// keys take few values (a chunk of 64 cell-sorted particles lands in a few window slots).
+__device__ __forceinline__ unsigned long long match_key_few(int key, bool act) {
+  unsigned long long todo = __ballot(act);
+  unsigned long long mine = 0ull;
+  while (todo) {  // wave-uniform
+    const int first = __ffsll(static_cast<long long>(todo)) - 1;
+    const int k0 = __builtin_amdgcn_readlane(key, first);
+    // lanes holding k0 (one compare into a scalar mask), restricted to the active ones
+    const unsigned long long m =
+        __builtin_amdgcn_uicmp(static_cast<unsigned>(key), static_cast<unsigned>(k0), 32) &
+        todo;
+    if (act && key == k0) mine = m;
+    todo &= ~m;
+  }
+  return mine;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll

@@ -981,15 +981,19 @@ __device__ __forceinline__ void deposit_weights(typename Part<P>::real pos,
   }
 }
 
+// Chunks of 64 particles per pass of a wave's loop.  Besides keeping loads in flight, a
+// longer pass writes more of a wave's output sub-run of each cell at once: the sub-run's
+// cache lines are then completed by fewer partial writes spread over less time (measured
+// against 1-8 on the large discharge).
 template <class P>
 struct MainU;
 template <>
 struct MainU<P32> {
-  static constexpr int value = 2;
+  static constexpr int value = 6;
 };
 template <>
 struct MainU<P64> {
-  static constexpr int value = 1;
+  static constexpr int value = 3;
 };
 
 template <class P>
@@ -1134,7 +1138,6 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       }
       qn = 0;
     };
-    const int nbits = key_bits(W);
     auto cell_body = [&](auto rev_tag, const Part<P>& q, uint32_t i, bool valid) {
       constexpr bool kRev = decltype(rev_tag)::value;
       int d = 0;
@@ -1145,7 +1148,7 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       const bool near = k >= 0;
       // stable rank inside this wave's unit of the order (from the unit's end backwards
       // for a backward wave)
-      const unsigned long long m = match_key(k, near, nbits);
+      const unsigned long long m = match_key_few(k, near);
       const int rank = __popcll(m & (kRev ? gt : lt));
       uint32_t dst = sink;
       if (near) {
