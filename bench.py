@@ -35,7 +35,7 @@ REC_BYTES = {"fp32_offset": 24, "fp64": 36}
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels_step.hip", "device_common.h", "sim_layout.h"):
+    for f in ("kernels_step.hip", "device_common.h", "sim_layout.h", "physics_host.cpp"):
         with open(os.path.join(ROOT, "paper_1104_3998_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -55,6 +55,9 @@ def read_traffic(precision):
     return float(m_b.group(1))
 
 
+PROGRESS_STEPS = 0  # --progress N: report every N warm-up steps
+
+
 def _psteps(sim):
     return sum(sum(sim.diagnostics(d).particle_steps) for d in range(len(sim.workloads)))
 
@@ -71,7 +74,14 @@ def _timed_run(fs, torch, wls, precision, steps, warmup, graph_k, profile, tunin
         sim.set_graph(graph_k)
     if profile:
         sim.profile(True)
-    sim.step(warmup)
+    done = 0
+    while done < warmup:  # in pieces, so a slow (profiled) run reports its progress
+        k = min(PROGRESS_STEPS, warmup - done) if PROGRESS_STEPS else warmup
+        sim.step(k)
+        done += k
+        if PROGRESS_STEPS:
+            sim.sync()
+            print("bench: warm-up %d/%d steps" % (done, warmup), file=sys.stderr, flush=True)
     sim.sync()
     if profile:
         sim.profile(True)  # drop the warm-up steps from the totals
@@ -149,7 +159,11 @@ def main():
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: a plain device copy of known size that calibrates the HBM "
                          "byte counters of rocprofv3")
+    ap.add_argument("--progress", type=int, default=0,
+                    help="report every N warm-up steps on stderr (for slow profiled runs)")
     args = ap.parse_args()
+    global PROGRESS_STEPS
+    PROGRESS_STEPS = max(0, args.progress)
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs a discharge (or a batch of "
               "discharges) on a single MI355X; --gpus %d is not supported" % args.gpus,
