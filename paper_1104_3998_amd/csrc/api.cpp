@@ -42,11 +42,14 @@ struct Plan {
   std::vector<SpeciesDev> sp;
   std::vector<DischargeDev> ds;
   std::vector<int2> tile_table;
+  std::vector<int2> node_table, cell_table;  // blocks of nodes / cells per species
   SimDev sim{};
   SimDev* d_sim = nullptr;
   SpeciesDev* d_sp = nullptr;
   DischargeDev* d_ds = nullptr;
   int2* d_tt = nullptr;
+  int2* d_nt = nullptr;
+  int2* d_ct = nullptr;
   LaunchInfo li{};
   size_t bytes = 0;
 };
@@ -241,10 +244,24 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   pl->d_ds = cv.take<DischargeDev>(n);
   pl->d_sp = cv.take<SpeciesDev>(2 * n);
   pl->d_tt = cv.take<int2>(pl->tile_table.size());
+  // the per-node and per-cell kernels take only the blocks that exist (a batch of
+  // discharges of different sizes would otherwise launch its largest size for every one);
+  // k_combine takes kCombineNodes nodes per workgroup, k_scan_cells a cell per wave
+  pl->node_table.clear();
+  pl->cell_table.clear();
+  for (int i = 0; i < 2 * n; ++i) {
+    for (int j = 0; j < pl->sp[i].n_nodes; j += kCombineNodes)
+      pl->node_table.push_back(make_int2(i, j));
+    for (int c = 0; c < pl->sp[i].n_cells; c += kWaves) pl->cell_table.push_back(make_int2(i, c));
+  }
+  pl->d_nt = cv.take<int2>(pl->node_table.size());
+  pl->d_ct = cv.take<int2>(pl->cell_table.size());
   pl->d_sim = cv.take<SimDev>(1);
   pl->sim.ds = pl->d_ds;
   pl->sim.sp = pl->d_sp;
   pl->sim.tile_table = pl->d_tt;
+  pl->sim.node_table = pl->d_nt;
+  pl->sim.cell_table = pl->d_ct;
   pl->bytes = align_up(cv.off, 256);
   LaunchInfo& li = pl->li;
   li.n_ds = n;
@@ -255,6 +272,8 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   li.n_gtiles = n_gtiles;
   li.max_cells = max_cells;
   li.max_window = max_window;
+  li.n_node_wgs = static_cast<int>(pl->node_table.size());
+  li.n_cell_wgs = static_cast<int>(pl->cell_table.size());
   li.fp32 = fp32;
   return PIC_OK;
 }
@@ -431,6 +450,10 @@ extern "C" int pic_init(const pic_config* cfgs, int n, void* d_workspace, size_t
   INITCHECK(hipMemcpyAsync(pl.d_sp, pl.sp.data(), sizeof(SpeciesDev) * pl.sp.size(),
                            hipMemcpyHostToDevice, st));
   INITCHECK(hipMemcpyAsync(pl.d_tt, pl.tile_table.data(), sizeof(int2) * pl.tile_table.size(),
+                           hipMemcpyHostToDevice, st));
+  INITCHECK(hipMemcpyAsync(pl.d_nt, pl.node_table.data(), sizeof(int2) * pl.node_table.size(),
+                           hipMemcpyHostToDevice, st));
+  INITCHECK(hipMemcpyAsync(pl.d_ct, pl.cell_table.data(), sizeof(int2) * pl.cell_table.size(),
                            hipMemcpyHostToDevice, st));
   INITCHECK(hipMemcpyAsync(pl.d_sim, &pl.sim, sizeof(SimDev), hipMemcpyHostToDevice, st));
   for (const SpeciesDev& S : pl.sp)

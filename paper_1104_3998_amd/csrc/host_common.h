@@ -22,6 +22,7 @@ double ion_mass(const pic_config& c);
 // Launch geometry the host needs beside the device descriptors.
 struct LaunchInfo {
   int n_ds, n_spec, total_tiles, max_nodes, max_cap, n_gtiles, max_cells, max_window;
+  int n_node_wgs, n_cell_wgs;  // entries of the node and cell block tables
   bool fp32;
 };
 

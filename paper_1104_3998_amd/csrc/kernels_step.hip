@@ -413,29 +413,36 @@ __device__ __forceinline__ bool diag_step(const DischargeDev& dd, unsigned long 
 
 // ====================================================================================
 // k_combine: w_s[j] = sum over the tiles whose deposit window holds node j + the far /
-// birth deposits.  One wave per node; the sum runs in a fixed reduction tree, so it is
-// reproducible.  Grid: (node blocks, species).
+// birth deposits.  kCombineLanes lanes per node (a node is covered by about (W + 1) / C
+// windows): lane l adds windows l, l + kCombineLanes, ... in order, then the lanes' sums
+// meet in a fixed butterfly, so the result is reproducible.  Grid: one workgroup per
+// block of kCombineNodes nodes of a species (node_table).
 // ====================================================================================
 template <class real>
-__global__ __launch_bounds__(256) void k_combine(const SimDev* __restrict__ simp) {
+__global__ __launch_bounds__(kCombineNodes * kCombineLanes) void k_combine(
+    const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev s = sim.sp[blockIdx.y];
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * kWaves + wave_id();  // one wave per node
-  if (j >= s.n_nodes) return;
+  const int2 nt = sim.node_table[blockIdx.x];
+  const SpeciesDev s = sim.sp[nt.x];
+  const int l = static_cast<int>(threadIdx.x) % kCombineLanes;
+  const int j = nt.y + static_cast<int>(threadIdx.x) / kCombineLanes;
+  const bool live = j < s.n_nodes;  // the butterfly below needs every lane of a node
   const real GM* part = static_cast<const real GM*>(s.partial);
   const int span = s.W + 1;
-  int a[2], b[2];
-  covering_ranges(s, j, span, a, b);
-  const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
-  const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
   double sum = 0.0;
-  for (int u = lane; u < n0 + n1; u += 64) {
-    const int t = u < n0 ? a[0] + u : a[1] + (u - n0);
-    sum += static_cast<double>(part[static_cast<size_t>(t) * span + covering_slot(s, j, t)]);
+  if (live) {
+    int a[2], b[2];
+    covering_ranges(s, j, span, a, b);
+    const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
+    const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
+    for (int u = l; u < n0 + n1; u += kCombineLanes) {
+      const int t = u < n0 ? a[0] + u : a[1] + (u - n0);
+      sum += static_cast<double>(part[static_cast<size_t>(t) * span + covering_slot(s, j, t)]);
+    }
   }
-  sum = wave_sum(sum);
-  if (lane == 0) sim.ds[s.ds].w[s.sp][j] = sum + s.far_w[j];
+#pragma unroll
+  for (int o = kCombineLanes / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (live && l == 0) sim.ds[s.ds].w[s.sp][j] = sum + s.far_w[j];
 }
 
 // ====================================================================================
@@ -675,9 +682,10 @@ constexpr uint32_t kMaxFarGroup = 8192;
 // the order of the stable sort), and a wave scan gives every unit its offset.
 __global__ __launch_bounds__(256) void k_scan_cells(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
-  const SpeciesDev s = sim.sp[blockIdx.y];
+  const int2 ct = sim.cell_table[blockIdx.x];
+  const SpeciesDev s = sim.sp[ct.x];
   const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * kWaves + wave_id();
+  const int c = ct.y + wave_id();
   const int N = s.n_cells;
   if (c >= N) return;
   const int W = s.W;
@@ -1492,9 +1500,9 @@ static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e
 
 void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
-  const dim3 grid((li.max_nodes + kWaves - 1) / kWaves, li.n_spec);
-  if (li.fp32) launch(k_combine<float>, grid, dim3(256), st, e0, e1, sim);
-  else launch(k_combine<double>, grid, dim3(256), st, e0, e1, sim);
+  const dim3 grid(li.n_node_wgs), block(kCombineNodes * kCombineLanes);
+  if (li.fp32) launch(k_combine<float>, grid, block, st, e0, e1, sim);
+  else launch(k_combine<double>, grid, block, st, e0, e1, sim);
 }
 
 void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st,
@@ -1511,7 +1519,7 @@ void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 
 void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
-  launch(k_scan_cells, dim3((li.max_cells + kWaves - 1) / kWaves, li.n_spec), dim3(256), st, e0,
+  launch(k_scan_cells, dim3(li.n_cell_wgs), dim3(256), st, e0,
          static_cast<hipEvent_t>(nullptr), sim);
   launch(k_scan_base, dim3(li.n_spec), dim3(kSolveWG), st, static_cast<hipEvent_t>(nullptr),
          e1, sim);

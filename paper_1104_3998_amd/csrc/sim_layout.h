@@ -34,6 +34,8 @@ constexpr int kWG = 256;             // threads per workgroup of the particle ke
 constexpr int kWaves = kWG / 64;     // wave64
 constexpr int kMaxWindow = 256;      // histogram window W = C + 2D (8-bit slot keys)
 constexpr int kSolveWG = 1024;       // threads of the per-discharge solve / scan kernels
+constexpr int kCombineLanes = 8;     // lanes per node in k_combine
+constexpr int kCombineNodes = 32;    // nodes of a k_combine workgroup (256 threads)
 constexpr int kMaxCells = 16384;     // LDS histogram of the general (initial) sort
 constexpr int kMaxEedfBins = 256;
 constexpr int kMaxCellsPerTile = 64;
@@ -140,6 +142,8 @@ struct SimDev {
   const DischargeDev CM* ds;
   const SpeciesDev CM* sp;
   const int2 CM* tile_table;  // workgroup -> (species index, local tile)
+  const int2 CM* node_table;  // k_combine workgroup -> (species index, first of kCombineNodes nodes)
+  const int2 CM* cell_table;  // k_scan_cells workgroup -> (species index, first of kWaves cells)
 };
 
 }  // namespace fspic
