@@ -246,13 +246,14 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   pl->d_tt = cv.take<int2>(pl->tile_table.size());
   // the per-node and per-cell kernels take only the blocks that exist (a batch of
   // discharges of different sizes would otherwise launch its largest size for every one);
-  // k_combine takes kCombineNodes nodes per workgroup, k_scan_cells a cell per wave
+  // k_combine takes kCombineNodes nodes per workgroup, k_scan_cells kScanCells cells
   pl->node_table.clear();
   pl->cell_table.clear();
   for (int i = 0; i < 2 * n; ++i) {
     for (int j = 0; j < pl->sp[i].n_nodes; j += kCombineNodes)
       pl->node_table.push_back(make_int2(i, j));
-    for (int c = 0; c < pl->sp[i].n_cells; c += kWaves) pl->cell_table.push_back(make_int2(i, c));
+    for (int c = 0; c < pl->sp[i].n_cells; c += kScanCells)
+      pl->cell_table.push_back(make_int2(i, c));
   }
   pl->d_nt = cv.take<int2>(pl->node_table.size());
   pl->d_ct = cv.take<int2>(pl->cell_table.size());

@@ -678,34 +678,47 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
 // ====================================================================================
 constexpr uint32_t kMaxFarGroup = 8192;
 
-// One wave per cell: lane u takes the u-th covering (tile, wave) unit of the cell (in
-// the order of the stable sort), and a wave scan gives every unit its offset.
-__global__ __launch_bounds__(256) void k_scan_cells(const SimDev* __restrict__ simp) {
+// kScanLanes lanes per cell: lane u takes the covering (tile, wave) units u, u + kScanLanes,
+// ... of the cell (in the order of the stable sort), and a scan over the cell's lanes gives
+// every unit its offset.  Grid: one workgroup per block of kScanCells cells of a species.
+template <class T>
+__device__ __forceinline__ T group_inclusive_scan(T x) {  // over aligned groups of kScanLanes
+  const int g = static_cast<int>(threadIdx.x) & (kScanLanes - 1);
+#pragma unroll
+  for (int o = 1; o < kScanLanes; o <<= 1) {
+    const T y = __shfl_up(x, o, kScanLanes);
+    if (g >= o) x = x + y;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(kScanCells * kScanLanes) void k_scan_cells(
+    const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
   const int2 ct = sim.cell_table[blockIdx.x];
   const SpeciesDev s = sim.sp[ct.x];
-  const int lane = threadIdx.x & 63;
-  const int c = ct.y + wave_id();
+  const int g = static_cast<int>(threadIdx.x) & (kScanLanes - 1);
+  const int c = ct.y + static_cast<int>(threadIdx.x) / kScanLanes;
   const int N = s.n_cells;
-  if (c >= N) return;
+  const bool live = c < N;  // the group scans below need every lane of a cell
   const int W = s.W;
-  int a[2], b[2];
-  covering_ranges(s, c, W, a, b);
+  int a[2] = {0, 0}, b[2] = {-1, -1};
+  if (live) covering_ranges(s, c, W, a, b);
   const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
   const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
   const int units = (n0 + n1) * kWaves;
-  const int rows = s.n_tail * kWaves;
+  const int rows = live ? s.n_tail * kWaves : 0;
   // Loads of up to kB passes are issued together, then scanned: one memory round trip
-  // for the usual cell (at most 64 kB units and tail rows).
+  // for the usual cell (at most kB * kScanLanes units and tail rows).
   constexpr int kB = 4;
   uint32_t run = 0;
-  const uint32_t nfar = s.far_cell_cnt[c];
-  for (int u0 = 0; u0 < units; u0 += 64 * kB) {
+  const uint32_t nfar = live ? s.far_cell_cnt[c] : 0u;
+  for (int u0 = 0; __any(u0 < units); u0 += kScanLanes * kB) {
     uint32_t v[kB];
     size_t o[kB];
 #pragma unroll
     for (int q = 0; q < kB; ++q) {
-      const int u = u0 + q * 64 + lane;
+      const int u = u0 + q * kScanLanes + g;
       v[q] = 0u;
       o[q] = 0;
       if (u < units) {
@@ -717,33 +730,33 @@ __global__ __launch_bounds__(256) void k_scan_cells(const SimDev* __restrict__ s
     }
 #pragma unroll
     for (int q = 0; q < kB; ++q) {
-      const int u = u0 + q * 64 + lane;
-      const uint32_t inc = wave_inclusive_scan(v[q]);
+      const int u = u0 + q * kScanLanes + g;
+      const uint32_t inc = group_inclusive_scan(v[q]);
       if (u < units) s.tilerel[o[q]] = run + inc - v[q];
-      run += __shfl(inc, 63, 64);
+      run += __shfl(inc, kScanLanes - 1, kScanLanes);
     }
   }
   run += nfar;
-  for (int j0 = 0; j0 < rows; j0 += 64 * kB) {
+  for (int j0 = 0; __any(j0 < rows); j0 += kScanLanes * kB) {
     uint32_t v[kB];
 #pragma unroll
     for (int q = 0; q < kB; ++q) {
-      const int jj = j0 + q * 64 + lane;
+      const int jj = j0 + q * kScanLanes + g;
       v[q] = jj < rows ? s.thist[static_cast<size_t>(jj) * N + c] : 0u;
     }
 #pragma unroll
     for (int q = 0; q < kB; ++q) {
-      const int jj = j0 + q * 64 + lane;
-      const uint32_t inc = wave_inclusive_scan(v[q]);
+      const int jj = j0 + q * kScanLanes + g;
+      const uint32_t inc = group_inclusive_scan(v[q]);
       if (jj < rows) {
         const size_t o = static_cast<size_t>(jj) * N + c;
         s.trel[o] = run + inc - v[q];
         s.thist[o] = 0u;
       }
-      run += __shfl(inc, 63, 64);
+      run += __shfl(inc, kScanLanes - 1, kScanLanes);
     }
   }
-  if (lane == 0) s.base[c] = run;
+  if (live && g == 0) s.base[c] = run;
 }
 
 __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict__ simp) {
@@ -1519,7 +1532,7 @@ void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 
 void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
-  launch(k_scan_cells, dim3(li.n_cell_wgs), dim3(256), st, e0,
+  launch(k_scan_cells, dim3(li.n_cell_wgs), dim3(kScanCells * kScanLanes), st, e0,
          static_cast<hipEvent_t>(nullptr), sim);
   launch(k_scan_base, dim3(li.n_spec), dim3(kSolveWG), st, static_cast<hipEvent_t>(nullptr),
          e1, sim);

@@ -36,6 +36,8 @@ constexpr int kMaxWindow = 256;      // histogram window W = C + 2D (8-bit slot 
 constexpr int kSolveWG = 1024;       // threads of the per-discharge solve / scan kernels
 constexpr int kCombineLanes = 8;     // lanes per node in k_combine
 constexpr int kCombineNodes = 32;    // nodes of a k_combine workgroup (256 threads)
+constexpr int kScanLanes = 16;       // lanes per cell in k_scan_cells
+constexpr int kScanCells = 16;       // cells of a k_scan_cells workgroup (256 threads)
 constexpr int kMaxCells = 16384;     // LDS histogram of the general (initial) sort
 constexpr int kMaxEedfBins = 256;
 constexpr int kMaxCellsPerTile = 64;
@@ -143,7 +145,7 @@ struct SimDev {
   const SpeciesDev CM* sp;
   const int2 CM* tile_table;  // workgroup -> (species index, local tile)
   const int2 CM* node_table;  // k_combine workgroup -> (species index, first of kCombineNodes nodes)
-  const int2 CM* cell_table;  // k_scan_cells workgroup -> (species index, first of kWaves cells)
+  const int2 CM* cell_table;  // k_scan_cells workgroup -> (species index, first of kScanCells cells)
 };
 
 }  // namespace fspic
