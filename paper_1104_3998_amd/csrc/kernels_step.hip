@@ -1325,13 +1325,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   }
   __shared__ uint32_t bq[kWaves + 1];
   __shared__ uint32_t coll[3];
-  __shared__ uint32_t births;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    coll[0] = coll[1] = coll[2] = 0u;
-    births = 0u;
-  }
+  if (tid == 0) coll[0] = coll[1] = coll[2] = 0u;
   __syncthreads();
+  uint32_t births = 0u;  // births staged so far (the same in every thread)
   const RecPtr out = rec_buf(&sim.sp[tt.x], pq);
   const RecPtr stage_e = rec_stage(&sim.sp[tt.x], 0);
   const RecPtr stage_i = rec_stage(&sim.sp[tt.x], 1);
@@ -1370,8 +1367,13 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
         }
       }
     }
-    uint32_t total;
-    const uint32_t pre = block_exclusive_scan<uint32_t>(born ? 1u : 0u, bq, total);
+    // ionizations are rare: most passes have none and need no scan for the staging order
+    const uint32_t total = static_cast<uint32_t>(__syncthreads_count(born ? 1 : 0));
+    uint32_t pre = 0u;
+    if (total) {
+      uint32_t t2;
+      pre = block_exclusive_scan<uint32_t>(born ? 1u : 0u, bq, t2);
+    }
     if (born) {
       const uint32_t si = r.lo + births + pre;
       if (si < s.cap) {
@@ -1391,9 +1393,7 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
         atomicOr(sim.error, kErrState);
       }
     }
-    __syncthreads();
-    if (tid == 0) births += total;
-    __syncthreads();
+    births += total;
   }
   if (tid == 0) {
     s.birth_cnt[tile] = births;
