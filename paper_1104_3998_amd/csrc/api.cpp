@@ -43,6 +43,7 @@ struct Plan {
   std::vector<DischargeDev> ds;
   std::vector<int2> tile_table;
   std::vector<int2> node_table, cell_table;  // blocks of nodes / cells per species
+  std::vector<int4> collide_table;           // MCC workgroups
   SimDev sim{};
   SimDev* d_sim = nullptr;
   SpeciesDev* d_sp = nullptr;
@@ -50,6 +51,7 @@ struct Plan {
   int2* d_tt = nullptr;
   int2* d_nt = nullptr;
   int2* d_ct = nullptr;
+  int4* d_cw = nullptr;
   LaunchInfo li{};
   size_t bytes = 0;
 };
@@ -194,7 +196,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.cand = cv.take<char>((fp32 ? 32 : 48) * cap1);
       S.cand_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
       S.birth_cnt = cv.take<uint32_t>(ntt);
-      S.tile_first = cv.take<uint32_t>(ntt);
+      S.stage_first = cv.take<uint32_t>(ntt);
       // births of both species are ranked over the electron tiles
       const int ntt_e = pl->tiles[2 * d].n_tiles + pl->tiles[2 * d].n_tail;
       S.birth_base = cv.take<uint32_t>(std::max(ntt, ntt_e) + 1);
@@ -255,14 +257,32 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
     for (int c = 0; c < pl->sp[i].n_cells; c += kScanCells)
       pl->cell_table.push_back(make_int2(i, c));
   }
+  // MCC work: each electron tile alone (a few thousand candidates); the ion tiles' short
+  // lists kIonGroup tiles at a time when there are many of them (measured: the ion
+  // workgroups of one large discharge run for free beside the long electron ones, while
+  // the tens of thousands of a batch pay for their count); electron work first, the long
+  // workgroups starting early
+  int ion_tiles = 0;
+  for (int i = 1; i < 2 * n; i += 2) ion_tiles += pl->sp[i].n_tiles + pl->sp[i].n_tail;
+  const int ion_group = ion_tiles > kIonGroupAbove ? kIonGroup : 1;
+  pl->collide_table.clear();
+  for (int pass = 0; pass < 2; ++pass)
+    for (int i = pass; i < 2 * n; i += 2) {
+      const int nt = pl->sp[i].n_tiles + pl->sp[i].n_tail;
+      const int g = pass == 0 ? 1 : ion_group;
+      for (int t = 0; t < nt; t += g)
+        pl->collide_table.push_back(make_int4(i, t, std::min(g, nt - t), 0));
+    }
   pl->d_nt = cv.take<int2>(pl->node_table.size());
   pl->d_ct = cv.take<int2>(pl->cell_table.size());
+  pl->d_cw = cv.take<int4>(pl->collide_table.size());
   pl->d_sim = cv.take<SimDev>(1);
   pl->sim.ds = pl->d_ds;
   pl->sim.sp = pl->d_sp;
   pl->sim.tile_table = pl->d_tt;
   pl->sim.node_table = pl->d_nt;
   pl->sim.cell_table = pl->d_ct;
+  pl->sim.collide_table = pl->d_cw;
   pl->bytes = align_up(cv.off, 256);
   LaunchInfo& li = pl->li;
   li.n_ds = n;
@@ -275,6 +295,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   li.max_window = max_window;
   li.n_node_wgs = static_cast<int>(pl->node_table.size());
   li.n_cell_wgs = static_cast<int>(pl->cell_table.size());
+  li.n_collide_wgs = static_cast<int>(pl->collide_table.size());
   li.fp32 = fp32;
   return PIC_OK;
 }
@@ -456,6 +477,8 @@ extern "C" int pic_init(const pic_config* cfgs, int n, void* d_workspace, size_t
                            hipMemcpyHostToDevice, st));
   INITCHECK(hipMemcpyAsync(pl.d_ct, pl.cell_table.data(), sizeof(int2) * pl.cell_table.size(),
                            hipMemcpyHostToDevice, st));
+  INITCHECK(hipMemcpyAsync(pl.d_cw, pl.collide_table.data(),
+                           sizeof(int4) * pl.collide_table.size(), hipMemcpyHostToDevice, st));
   INITCHECK(hipMemcpyAsync(pl.d_sim, &pl.sim, sizeof(SimDev), hipMemcpyHostToDevice, st));
   for (const SpeciesDev& S : pl.sp)
     INITCHECK(hipMemcpyAsync(S.next_id, &S.n_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));

@@ -23,6 +23,7 @@ double ion_mass(const pic_config& c);
 struct LaunchInfo {
   int n_ds, n_spec, total_tiles, max_nodes, max_cap, n_gtiles, max_cells, max_window;
   int n_node_wgs, n_cell_wgs;  // entries of the node and cell block tables
+  int n_collide_wgs;           // entries of the MCC work table
   bool fp32;
 };
 

@@ -232,13 +232,22 @@ struct WaveRange {
   uint32_t lo, hi;
 };
 
-__device__ __forceinline__ WaveRange wave_range(const TileRange& r, int w) {
+// piece w of a tile (any lane may ask for any piece)
+__device__ __forceinline__ WaveRange piece_range(const TileRange& r, int w) {
   const uint32_t n = r.hi - r.lo;
   const uint32_t q = (n + kWaves * 64 - 1) / (kWaves * 64) * 64;
   WaveRange wr;
-  // wave-uniform: keeps the particle loop a scalar loop
-  wr.lo = __builtin_amdgcn_readfirstlane(min(r.hi, r.lo + static_cast<uint32_t>(w) * q));
-  wr.hi = __builtin_amdgcn_readfirstlane(min(r.hi, wr.lo + q));
+  wr.lo = min(r.hi, r.lo + static_cast<uint32_t>(w) * q);
+  wr.hi = min(r.hi, wr.lo + q);
+  return wr;
+}
+
+// the piece of the calling wave, as wave-uniform values (keeps the particle loop a scalar
+// loop): w must be the same in every lane
+__device__ __forceinline__ WaveRange wave_range(const TileRange& r, int w) {
+  WaveRange wr = piece_range(r, w);
+  wr.lo = __builtin_amdgcn_readfirstlane(wr.lo);
+  wr.hi = __builtin_amdgcn_readfirstlane(wr.hi);
   return wr;
 }
 
@@ -1277,7 +1286,6 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
     }
   }
   if (tid == 0) {
-    s.tile_first[tile] = r.lo;
     if (sh.err) atomicOr(sim.error, sh.err);
     if (sh.abs_cnt[0]) atomicAdd(&s.absorbed[0], static_cast<unsigned long long>(sh.abs_cnt[0]));
     if (sh.abs_cnt[1]) atomicAdd(&s.absorbed[1], static_cast<unsigned long long>(sh.abs_cnt[1]));
@@ -1291,48 +1299,72 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
 
 // ====================================================================================
 // k_collide: modified null-collision MCC (Sec. 3.8, eq. null_collision) of the candidates
-// k_main found (word 0 of the particle's Philox block 0 below floor(P0 2^32)).  One
-// workgroup per tile takes the tile's candidates in input order (its waves' lists one
-// after the other), 256 at a time, so the collision path runs on full waves.  k_main
-// stored each candidate's post-push state beside its sorted slot; the post-collision
-// velocity is written to that slot.  Births are staged in the order of their parents
-// (= input order) and deposited; k_finalize appends them.
+// k_main found (word 0 of the particle's Philox block 0 below floor(P0 2^32)).  A
+// workgroup takes a part of the candidates in input order (the tiles' waves' lists one
+// after the other), 256 at a time, so the collision path runs on full waves:
+// * an electron tile's list (a few thousand candidates) by one workgroup (splitting it
+//   over two was measured slower);
+// * the ion tiles' lists (a handful of candidates each) up to kIonGroup tiles at a time
+//   when there are many: every workgroup pays the collision path's long dependent chain
+//   once per pass, however few lanes it has.
+// k_main stored each candidate's post-push state beside its sorted slot; the
+// post-collision velocity is written to that slot.  Births (electron ionization) are
+// staged in the order of their parents (= input order) and deposited; k_finalize appends
+// them.
 // ====================================================================================
 template <class P>
 __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
-  const int2 tt = sim.tile_table[blockIdx.x];
-  const SpeciesDev s = sim.sp[tt.x];
+  const int4 cw = sim.collide_table[blockIdx.x];  // (species, first tile, tiles, 0)
+  const SpeciesDev s = sim.sp[cw.x];
   const unsigned long long step = *sim.step;
   const uint32_t step32 = static_cast<uint32_t>(step);
   const int p = static_cast<int>(step & 1ull), pq = p ^ 1;
-  const int tile = tt.y;
+  const int tile = cw.y;
+  const bool electrons = s.sp == 0;
   const TileRange r = tile_range(s, tile, p);
-  uint32_t seg_lo[kWaves], seg_pre[kWaves + 1];
-  seg_pre[0] = 0u;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const WaveRange wr = wave_range(r, w);
-    const uint32_t nc = s.cand_cnt[tile * kWaves + w];
-    seg_lo[w] = wave_reversed(r, w) ? wr.hi - nc : wr.lo;  // see list_candidate in k_main
-    seg_pre[w + 1] = seg_pre[w] + nc;
-  }
-  const uint32_t n = seg_pre[kWaves];
-  if (n == 0u) {
-    if (threadIdx.x == 0) s.birth_cnt[tile] = 0u;
-    return;
-  }
+  // the (tile, wave) list segments of this workgroup's tiles, in input order
+  constexpr int kSeg = kIonGroup * kWaves;
+  __shared__ uint32_t sg_lo[kSeg], sg_pre[kSeg + 1];
   __shared__ uint32_t bq[kWaves + 1];
   __shared__ uint32_t coll[3];
   const int tid = threadIdx.x;
+  if (tid < kSeg) {
+    const int g = tid / kWaves, w = tid - g * kWaves;
+    uint32_t nc = 0u, lo = 0u;
+    if (g < cw.z) {
+      const TileRange rg = tile_range(s, tile + g, p);
+      const WaveRange wr = piece_range(rg, w);  // w differs between the lanes
+      nc = s.cand_cnt[(tile + g) * kWaves + w];
+      lo = wave_reversed(rg, w) ? wr.hi - nc : wr.lo;  // see list_candidate in k_main
+    }
+    // exclusive scan of the kSeg counts (lanes 0..kSeg-1 of wave 0)
+    uint32_t inc = nc;
+#pragma unroll
+    for (int o = 1; o < kSeg; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o, kSeg);
+      if (tid >= o) inc += y;
+    }
+    sg_lo[tid] = lo;
+    sg_pre[tid] = inc - nc;
+    if (tid == kSeg - 1) sg_pre[kSeg] = inc;
+  }
   if (tid == 0) coll[0] = coll[1] = coll[2] = 0u;
   __syncthreads();
+  const uint32_t n = sg_pre[kSeg];
+  if (n == 0u) {
+    if (tid == 0 && electrons) {
+      s.birth_cnt[tile] = 0u;
+      s.stage_first[tile] = r.lo;
+    }
+    return;
+  }
   uint32_t births = 0u;  // births staged so far (the same in every thread)
-  const RecPtr out = rec_buf(&sim.sp[tt.x], pq);
-  const RecPtr stage_e = rec_stage(&sim.sp[tt.x], 0);
-  const RecPtr stage_i = rec_stage(&sim.sp[tt.x], 1);
-  const SpeciesDev ion = sim.sp[s.sp == 0 ? tt.x + 1 : tt.x];  // used by electron tiles
+  const RecPtr out = rec_buf(&sim.sp[cw.x], pq);
+  const RecPtr stage_e = rec_stage(&sim.sp[cw.x], 0);
+  const RecPtr stage_i = rec_stage(&sim.sp[cw.x], 1);
+  const SpeciesDev ion = sim.sp[electrons ? cw.x + 1 : cw.x];  // used by electron tiles
   real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (s.W + 1);
   for (uint32_t b = 0; b < n; b += kWG) {
     const uint32_t e = b + tid;
@@ -1342,9 +1374,8 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     real vs[3] = {real(0), real(0), real(0)}, vi[3] = {real(0), real(0), real(0)};
     if (e < n) {
       int w = 0;
-#pragma unroll
-      for (int k = 1; k < kWaves; ++k) w += e >= seg_pre[k] ? 1 : 0;
-      const uint32_t idx = seg_lo[w] + (e - seg_pre[w]);
+      for (int k = 1; k < cw.z * kWaves; ++k) w += e >= sg_pre[k] ? 1 : 0;
+      const uint32_t idx = sg_lo[w] + (e - sg_pre[w]);
       real v[3] = {real(0), real(0), real(0)};
       const uint4 c = idx < s.cap ? cand_load<P>(s.cand, idx, pos, v)
                                   : make_uint4(kNoDest, 0u, 0u, 0u);
@@ -1396,7 +1427,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     births += total;
   }
   if (tid == 0) {
-    s.birth_cnt[tile] = births;
+    if (electrons) {
+      s.birth_cnt[tile] = births;
+      s.stage_first[tile] = r.lo;
+    }
     for (int k = 0; k < 3; ++k)
       if (coll[k]) atomicAdd(&s.collisions[k], static_cast<unsigned long long>(coll[k]));
   }
@@ -1458,15 +1492,15 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int lane = threadIdx.x & 63;
-  const int g = blockIdx.x * kWaves + wave_id();
+  const int g = blockIdx.x * kWaves + wave_id();  // one wave per tile
   const int q = static_cast<int>(*sim.step & 1ull);  // k_birth_scan advanced the step
   if (g < sim.total_tiles) {
     const int2 tt = sim.tile_table[g];
     const SpeciesDev se = sim.sp[tt.x];
     if (se.sp == 0) {
-      const int t = tt.y;
-      const uint32_t b0 = se.birth_base[t], b1 = se.birth_base[t + 1];
-      const uint32_t first = se.tile_first[t];
+      const int u = tt.y;
+      const uint32_t b0 = se.birth_base[u], b1 = se.birth_base[u + 1];
+      const uint32_t first = se.stage_first[u];
 #pragma unroll
       for (int sp = 0; sp < 2; ++sp) {
         const SpeciesDev s = sim.sp[tt.x + sp];
@@ -1546,8 +1580,9 @@ void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 
 void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
-  if (li.fp32) launch(k_collide<P32>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
-  else launch(k_collide<P64>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+  const dim3 grid(li.n_collide_wgs);
+  if (li.fp32) launch(k_collide<P32>, grid, dim3(kWG), st, e0, e1, sim);
+  else launch(k_collide<P64>, grid, dim3(kWG), st, e0, e1, sim);
 }
 
 void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,

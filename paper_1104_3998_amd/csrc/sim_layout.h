@@ -36,6 +36,8 @@ constexpr int kMaxWindow = 256;      // histogram window W = C + 2D (8-bit slot 
 constexpr int kSolveWG = 1024;       // threads of the per-discharge solve / scan kernels
 constexpr int kCombineLanes = 8;     // lanes per node in k_combine
 constexpr int kCombineNodes = 32;    // nodes of a k_combine workgroup (256 threads)
+constexpr int kIonGroup = 4;         // ion tiles whose candidate lists one MCC workgroup takes
+constexpr int kIonGroupAbove = 8192; // ... when a simulation has more ion tiles than this
 constexpr int kScanLanes = 16;       // lanes per cell in k_scan_cells
 constexpr int kScanCells = 16;       // cells of a k_scan_cells workgroup (256 threads)
 constexpr int kMaxCells = 16384;     // LDS histogram of the general (initial) sort
@@ -92,7 +94,7 @@ struct SpeciesDev {
                                // stored in the input-index range of the wave that found them
   uint32_t GM* cand_cnt;       // [(n_tiles + n_tail) * kWaves] candidates per (tile, wave)
   uint32_t GM* birth_cnt;      // [n_tiles + n_tail] births of each electron tile
-  uint32_t GM* tile_first;     // [n_tiles + n_tail] first input index of each tile
+  uint32_t GM* stage_first;    // [n_tiles + n_tail] first staging index of a tile's births
   uint32_t GM* birth_base;     // [n_tiles + n_tail + 1] exclusive scan of the electron births
                                // (electron species only)
   uint32_t GM* fin;            // [2] births that fit this step, id of the first
@@ -146,6 +148,9 @@ struct SimDev {
   const int2 CM* tile_table;  // workgroup -> (species index, local tile)
   const int2 CM* node_table;  // k_combine workgroup -> (species index, first of kCombineNodes nodes)
   const int2 CM* cell_table;  // k_scan_cells workgroup -> (species index, first of kScanCells cells)
+  // k_collide workgroup -> (species index, first tile, tiles, 0): one electron tile, or up
+  // to kIonGroup consecutive ion tiles
+  const int4 CM* collide_table;
 };
 
 }  // namespace fspic
