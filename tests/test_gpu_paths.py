@@ -113,6 +113,33 @@ def test_batched_discharges_match_oracle_each(fspic, oracle_mod):
     sim.close()
 
 
+def test_grouped_ion_mcc_matches_oracle(fspic, oracle_mod):
+    """Five 2048-cell discharges at 100 Pa with one-cell ion tiles: 10320 ion tiles, more
+    than the 8192 above which the MCC pass takes four ion tiles' candidate lists (about
+    1000 ion candidates per discharge, P0 = 0.05) per workgroup.  One step from seeded
+    states with an unsorted births tail matches every discharge's oracle at the FP64 bar,
+    ion collisions included."""
+    wls = [workloads.bounded(2048, 20000, 300.0, 100.0, discharge=k, seed=k, steps=10)
+           for k in range(5)]
+    print("grouped ion MCC", flush=True)
+    sim = fspic.Simulation(wls, "fp64", tuning={"cells_per_tile": (0, 1)})
+    states = [workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), "fp64",
+                                        seed=200 + d, tail=(64, 64), step=0)
+              for d, wl in enumerate(wls)]
+    orcs = []
+    for d, wl in enumerate(wls):
+        sim.set_state(states[d], d)
+        orcs.append(oracle_from_state(oracle_mod, wl, states[d], False))
+    gbs = [tallies_of(sim.diagnostics(d)) for d in range(len(wls))]
+    sim.step(1)
+    for d, o in enumerate(orcs):
+        o.step(1)
+        compare_fp64(sim, o, "grouped ion MCC %d" % d, gbase=gbs[d], d=d)
+        ion_coll = sum(tallies_of(sim.diagnostics(d))[1]["coll"]) - sum(gbs[d][1]["coll"])
+        assert ion_coll > 0, d
+    sim.close()
+
+
 def test_graph_replay_equals_eager(fspic):
     wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0)
     a = fspic.Simulation(wl, "fp64")
