@@ -129,6 +129,73 @@ def run_path(fs, torch, wls, precision, steps, warmup, graph_k=50, tuning=None,
             "steps": steps}
 
 
+def _averages(fs, torch, wl, precision, steps, tuning=None, state=None):
+    """Time-averaged n_e, n_i, Phi (over the workload's averaging window) and the EEDF
+    histogram after `steps` graph-replayed steps from the seeded load (or from `state`)."""
+    import numpy as np
+    sim = fs.Simulation(wl, precision, tuning=tuning)
+    if state is not None:
+        sim.set_state(state)
+    sim.set_graph(50)
+    sim.step(steps)
+    sim.sync()
+    out = {"n_e": sim.density("n_e", kind=1), "n_i": sim.density("n_i", kind=1),
+           "phi": sim.density("phi", kind=1), "eedf": sim.grid("eedf").astype(np.float64)}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def density_gate(fs, torch, workloads, steps):
+    """The accuracy gate of the metric: the FP32 cell + offset path against the FP64 path,
+    same seed and the same load (the FP32 state is the FP64 draw rounded), time-averaged
+    n_e, n_i and Phi over the second half of `steps` steps of the large discharge and the
+    normalised EEDF, compared by rel-L2 over nodes (bins).  Two FP64 controls give the
+    floors such a comparison cannot go below: another tile geometry (round-off chaos
+    alone) and seed + 1 (the statistical floor); a third starts the FP64 path from the
+    FP32-rounded load, which isolates what a 1e-7 perturbation of the state does by
+    itself (through the collision decisions it flips)."""
+    import numpy as np
+
+    def rel_l2(a, b):
+        if "eedf" in a:
+            a = dict(a, eedf=a["eedf"] / max(a["eedf"].sum(), 1.0))
+            b = dict(b, eedf=b["eedf"] / max(b["eedf"].sum(), 1.0))
+        return {k: float(np.linalg.norm(a[k] - b[k]) / max(np.linalg.norm(b[k]), 1e-300))
+                for k in ("n_e", "n_i", "phi", "eedf")}
+
+    wl = workloads.large_c3(avg_start=steps // 2)
+    ref = _averages(fs, torch, wl, "fp64", steps)
+    f32 = _averages(fs, torch, wl, "fp32_offset", steps)
+    tiles = _averages(fs, torch, wl, "fp64", steps, tuning={"cells_per_tile": (4, 2)})
+    seed1 = _averages(fs, torch, workloads.large_c3(avg_start=steps // 2, seed=1), "fp64",
+                      steps)
+    sim = fs.Simulation(wl, "fp32_offset")
+    st = sim.get_state()
+    sim.close()
+    del sim
+    st64 = {"step": st["step"], "next_id": st["next_id"]}
+    for s in (0, 1):
+        a = st[s]
+        st64[s] = {"x": a["cell"].astype(np.float64) + a["off"].astype(np.float64),
+                   "vx": a["vxf"].astype(np.float64), "vy": a["vyf"].astype(np.float64),
+                   "vz": a["vzf"].astype(np.float64), "id": a["id"], "n": a["n"],
+                   "n_sorted": a["n_sorted"]}
+    del st
+    pert = _averages(fs, torch, wl, "fp64", steps, state=st64)
+    del st64
+    d32 = rel_l2(f32, ref)
+    return {"workload": "large single discharge, %d steps from the load, averages over "
+                        "steps %d..%d" % (steps, steps // 2, steps),
+            "fp32_offset_vs_fp64": d32,
+            "floor_fp64_other_tiles": rel_l2(tiles, ref),
+            "floor_fp64_seed_plus_1": rel_l2(seed1, ref),
+            "fp64_from_fp32_rounded_load": rel_l2(pert, ref),
+            "max_fp32_offset_vs_fp64": max(d32.values()),
+            "within_1e-3": max(d32.values()) <= 1e-3}
+
+
 def cpu_baseline(wl, steps):
     import oracle
     orc = oracle.Oracle(wl)
@@ -156,6 +223,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--path-steps", type=int, default=400)
     ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--gate-steps", type=int, default=2000,
+                    help="steps of the FP32-vs-FP64 density gate runs (0: skip)")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: a plain device copy of known size that calibrates the HBM "
                          "byte counters of rocprofv3")
@@ -216,6 +285,11 @@ def main():
                             "eager_value": rb["eager_value"], "steps": args.path_steps,
                             "discharges": len(batch),
                             "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"]}
+    gate = None
+    if args.gate_steps > 0:
+        print("bench: density gate, FP32 cell+offset vs FP64, %d steps" % args.gate_steps,
+              file=sys.stderr, flush=True)
+        gate = density_gate(fs, torch, workloads, args.gate_steps)
     # roofline of the dominant kernel (k_main), FP32 path
     kmain_ms = head["kernel_ms"]["main"]
     ps_per_launch = head["eager_particle_steps"] / head["steps"]
@@ -249,6 +323,7 @@ def main():
                    "particles": 20_000_000, "n_cells": 4096, "graph_steps": 50},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "density_gate": gate,
         "paths": dict({"fp32_offset": {"value": head["value"], "ms_per_step": head["ms_per_step"],
                                        "eager_value": head["eager_value"],
                                        "particles_end": head["particles_end"],
