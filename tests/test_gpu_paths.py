@@ -175,3 +175,19 @@ def test_full_size_large_discharge_one_step(fspic, oracle_mod, precision):
                                    seed=23, vth=(2.2, 0.01), tail=(1000, 1000))
     one_step(fspic, oracle_mod, wl, st, precision, coll_slack=5 if fp32 else 0,
              label="full " + precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+def test_full_size_long_run_one_step(fspic, oracle_mod, precision):
+    """The long run's discharge at full size (8192 cells, 3.2e7 + 3.2e7 particles, 20 Pa)
+    with its default geometry: one-cell tiles for both species, so 8192 + 16 tail ion
+    tiles and the MCC pass groups the ion lists four at a time; about 1e7 collision
+    candidates.  One step from a seeded state against the oracle over every particle (the
+    FP32 layout may flip a handful of channel decisions, as in the large discharge)."""
+    wl = workloads.long_c5()
+    fp32 = precision == "fp32_offset"
+    print("long run full size", precision, flush=True)
+    st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
+                                   seed=29, vth=(2.2, 0.01), tail=(1000, 1000))
+    one_step(fspic, oracle_mod, wl, st, precision, coll_slack=8 if fp32 else 0,
+             label="long " + precision)
