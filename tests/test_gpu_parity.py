@@ -185,6 +185,7 @@ def small_rf(**kw):
 CASES = [
     ("periodic", workloads.periodic_c1()),
     ("rf_small", small_rf()),
+    ("rf_full", workloads.rf_c2()),  # the bounded RF discharge at its size: 2e5 + 2e5
 ]
 
 
