@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--path-steps", type=int, default=400)
     ap.add_argument("--batched-scale", type=float, default=1.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched path: the library's default tile geometry, untuned")
     ap.add_argument("--gate-steps", type=int, default=2000,
                     help="steps of the FP32-vs-FP64 density gate runs (0: skip)")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
@@ -279,12 +281,21 @@ def main():
         batch = workloads.batched_c4(scale=args.batched_scale)
         # the hottest discharges of the scan (55-95 Pa, 400-490 V, < 2.5 cm) more than
         # double their ion count within a few hundred steps
+        tuning, tune_rep = None, None
+        if not args.no_autotune:
+            # outside the timed region: the fastest of the rule's geometry and its scaled
+            # variants (cells per tile, window), timed on this batch
+            from paper_1104_3998_amd.autotune import autotune
+            tuning, tune_rep = autotune(batch, "fp32_offset", cap_factor=4.0,
+                                        log=lambda m: print("bench: " + m, file=sys.stderr,
+                                                            flush=True))
         rb = run_path(fs, torch, batch, "fp32_offset", args.path_steps, args.warmup,
-                      cap_factor=4.0)
+                      tuning=tuning, cap_factor=4.0)
         paths["batched"] = {"value": rb["value"], "ms_per_step": rb["ms_per_step"],
                             "eager_value": rb["eager_value"], "steps": args.path_steps,
                             "discharges": len(batch),
-                            "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"]}
+                            "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"],
+                            "autotune": tune_rep}
     gate = None
     if args.gate_steps > 0:
         print("bench: density gate, FP32 cell+offset vs FP64, %d steps" % args.gate_steps,

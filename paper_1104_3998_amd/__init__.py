@@ -194,7 +194,11 @@ class Simulation:
         self.workloads = [dict(w) for w in wls]
         self.precision = precision
         self.fp32 = precision == "fp32_offset"
-        self.cfgs = [make_config(w, precision, cap_factor, tuning) for w in wls]
+        # tuning: one dict for every discharge, or a list with one dict per discharge
+        tunings = tuning if isinstance(tuning, (list, tuple)) else [tuning] * len(wls)
+        if len(tunings) != len(wls):
+            raise ValueError("tuning list needs one entry per discharge")
+        self.cfgs = [make_config(w, precision, cap_factor, t) for w, t in zip(wls, tunings)]
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.bytes = workspace_bytes(self.cfgs)

@@ -123,3 +123,15 @@ def test_simulation_requires_gpu(fspic):
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         fspic.Simulation(workloads.periodic_c1())
+
+
+def test_autotune_geometry_scaling():
+    """The tuner's candidates are the library's rule scaled per species and clamped to
+    the limits the library accepts (1..64 cells per tile, window >= 1)."""
+    from paper_1104_3998_amd import autotune as at
+    rule = at.rule_geometry([workloads.large_c3()], "fp32_offset")
+    assert rule == [((8, 32), (1, 4))]
+    assert at.scaled_tuning(rule, 1.0, 1.0, 1.0) == [{"cells_per_tile": (8, 1), "window": (32, 4)}]
+    assert at.scaled_tuning(rule, 0.5, 2.0, 0.5) == [{"cells_per_tile": (4, 2), "window": (16, 4)}]
+    assert at.scaled_tuning([((64, 32), (1, 4))], 2.0, 0.5, 0.01) == \
+        [{"cells_per_tile": (64, 1), "window": (1, 4)}]

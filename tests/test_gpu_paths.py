@@ -191,3 +191,51 @@ def test_full_size_long_run_one_step(fspic, oracle_mod, precision):
                                    seed=29, vth=(2.2, 0.01), tail=(1000, 1000))
     one_step(fspic, oracle_mod, wl, st, precision, coll_slack=8 if fp32 else 0,
              label="long " + precision)
+
+
+def test_tile_geometry_does_not_change_results(fspic):
+    """The tile geometry (cells per tile, window) changes speed only: 20 FP64 steps of the
+    RF discharge with the default geometry and with half-size electron tiles, double-size
+    ion tiles and a half window give the same permutation, tallies and births, and the
+    same positions, velocities and node weights to 1e-12 (the deposit sums in another
+    order)."""
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0)
+    from paper_1104_3998_amd import autotune as at
+    alt = at.scaled_tuning(at.rule_geometry([wl], "fp64"), 0.5, 2.0, 0.5)
+    print("tile geometry", alt, flush=True)
+    a = fspic.Simulation(wl, "fp64")
+    b = fspic.Simulation(wl, "fp64", tuning=alt)
+    a.step(20)
+    b.step(20)
+    sa, sb = a.get_state(), b.get_state()
+    n = wl["n_cells"]
+    for s in (0, 1):
+        assert np.array_equal(sa[s]["id"], sb[s]["id"]), s
+        assert np.max(np.abs(sa[s]["x"] - sb[s]["x"]), initial=0) <= 1e-12 * n
+        for k in ("vx", "vy", "vz"):
+            scale = np.max(np.abs(sa[s][k]), initial=1e-30)
+            assert np.max(np.abs(sa[s][k] - sb[s][k]), initial=0) <= 1e-12 * scale
+        assert np.max(np.abs(sa[s]["w"] - sb[s]["w"])) <= 1e-12 * sa[s]["w"].max()
+    assert tallies_of(a.diagnostics()) == tallies_of(b.diagnostics())
+    a.close()
+    b.close()
+
+
+def test_autotune_and_cache(fspic, tmp_path):
+    """The tuner times the rule and its scaled variants on a small batch, returns one
+    tuning per discharge with a rate for the rule, and a second call with the same cache
+    file returns the stored choice."""
+    from paper_1104_3998_amd import autotune as at
+    wls = workloads.batched_c4(n_discharges=3, scale=0.01)
+    cache = str(tmp_path / "tune.json")
+    tun, rep = at.autotune(wls, "fp32_offset", steps=6, warmup=4, cap_factor=4.0,
+                           cache=cache, log=lambda m: print(m, flush=True))
+    assert len(tun) == 3 and rep["rule_rate"] > 0 and rep["best_rate"] >= rep["rule_rate"]
+    assert len(rep["timed"]) >= 4
+    tun2, rep2 = at.autotune(wls, "fp32_offset", steps=6, warmup=4, cap_factor=4.0,
+                             cache=cache)
+    assert tun2 == tun and rep2["best"] == rep["best"]
+    sim = fspic.Simulation(wls, "fp32_offset", tuning=tun, cap_factor=4.0)
+    sim.step(3)
+    sim.sync()
+    sim.close()
