@@ -239,3 +239,42 @@ def test_autotune_and_cache(fspic, tmp_path):
     sim.step(3)
     sim.sync()
     sim.close()
+
+
+EDGE_STATES = {
+    # every particle in one cell
+    "one_cell": dict(n=(4096, 4096), cells=[64], vth=(0.6, 0.01)),
+    # a quarter of the cells occupied, in two blocks: empty cells and empty tiles
+    "empty_cells": dict(n=(8192, 8192), cells=list(range(0, 16)) + list(range(100, 116))),
+    # one particle per species
+    "single": dict(n=(1, 1)),
+    # every electron a far mover (40-90 cells in one step against a 31-cell window)
+    "all_far": dict(n=(4096, 4096), fast=(4096, 0)),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+@pytest.mark.parametrize("case", sorted(EDGE_STATES))
+def test_edge_states_one_step(fspic, oracle_mod, case, precision):
+    """One step from degenerate states against the oracle: the sort, deposit, MCC and
+    solve on a single occupied cell, on empty cells and tiles, on one particle per
+    species, and with every electron beyond the sort window (far list sized for all)."""
+    e = EDGE_STATES[case]
+    wl = workloads.periodic_c1()
+    print("edge state", case, precision, flush=True)
+    st = workloads.synthetic_state(wl["n_cells"], e["n"], precision, seed=41,
+                                   vth=e.get("vth", (2.0, 0.02)), fast=e.get("fast", (0, 0)),
+                                   cells=e.get("cells"))
+    fp32 = precision == "fp32_offset"
+    sim = fspic.Simulation(wl, precision, tuning={"far_capacity": 8192})
+    sim.set_state(st)
+    orc = oracle_from_state(oracle_mod, wl, st, fp32)
+    gb = tallies_of(sim.diagnostics())
+    sim.step(1)
+    orc.step(1)
+    from test_gpu_parity import compare_fp32
+    if fp32:
+        compare_fp32(sim, orc, st, case, gbase=gb)
+    else:
+        compare_fp64(sim, orc, case, gbase=gb)
+    sim.close()

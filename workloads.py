@@ -117,12 +117,13 @@ def batched_c4(n_discharges=256, scale=1.0, **kw):
 
 
 def synthetic_state(n_cells, n_per_species, precision, seed, vth=(2.0, 0.02), tail=(0, 0),
-                    fast=(0, 0), fast_speed=(40.0, 90.0), step=5):
+                    fast=(0, 0), fast_speed=(40.0, 90.0), step=5, cells=None):
     """A seeded particle state in the library's layout, to hand to both the HIP path and
     the oracle.  Per species: uniform positions laid out cell by cell (so the first
     n - tail particles are in cell order by construction), then `tail` particles in random
     cells (an unsorted births tail); Gaussian velocities of spread vth (cells per step);
-    `fast` electrons moved to |v_x| in fast_speed; ids a random permutation.
+    `fast` electrons moved to |v_x| in fast_speed; ids a random permutation.  `cells` (an
+    ascending list) restricts the sorted part to those cells, leaving the others empty.
     Returns {0: arrays, 1: arrays, "step", "next_id"}; arrays hold x (float64) or
     cell/off (int32/float32) and vx, vy, vz, id, n, n_sorted."""
     rng = np.random.default_rng(seed)
@@ -131,8 +132,9 @@ def synthetic_state(n_cells, n_per_species, precision, seed, vth=(2.0, 0.02), ta
     for s, n in enumerate(n_per_species):
         n = int(n)
         nt = int(tail[s])
-        counts = rng.multinomial(n - nt, np.full(n_cells, 1.0 / n_cells))
-        cell = np.concatenate([np.repeat(np.arange(n_cells), counts),
+        occ = np.arange(n_cells) if cells is None else np.asarray(cells, dtype=np.int64)
+        counts = rng.multinomial(n - nt, np.full(occ.size, 1.0 / occ.size))
+        cell = np.concatenate([np.repeat(occ, counts),
                                rng.integers(0, n_cells, nt)]).astype(np.int32)
         if fp32:
             off = rng.random(n, dtype=np.float32)
