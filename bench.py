@@ -196,6 +196,23 @@ def density_gate(fs, torch, workloads, steps):
             "within_1e-3": max(d32.values()) <= 1e-3}
 
 
+def sequential_sample(fs, torch, wls, tuning, steps, warmup, every=16, cap_factor=4.0):
+    """The batched scan's alternative: the same discharges run one at a time, each from its
+    own load with its own HIP graph, timed over the same steps.  Every `every`-th discharge
+    is run; the aggregate rate is their particle-steps over their summed time."""
+    ps, secs, picked = 0, 0.0, list(range(0, len(wls), every))
+    for d in picked:
+        t = [tuning[d]] if isinstance(tuning, (list, tuple)) else tuning
+        r = _timed_run(fs, torch, [wls[d]], "fp32_offset", steps, warmup, 50, False, t,
+                       cap_factor)
+        ps += r["particle_steps"]
+        secs += r["ms_per_step"] * steps / 1e3
+    return {"value": ps / secs, "discharges_run": len(picked), "of": len(wls),
+            "steps": steps, "note": "every %dth discharge of the scan run alone, each "
+                                    "graph-replayed; rate = their particle-steps / their "
+                                    "summed time" % every}
+
+
 def cpu_baseline(wl, steps):
     import oracle
     orc = oracle.Oracle(wl)
@@ -296,6 +313,11 @@ def main():
                             "discharges": len(batch),
                             "particles": rb["particles_end"], "kernel_ms": rb["kernel_ms"],
                             "autotune": tune_rep}
+        print("bench: batched scan, discharges one at a time (sample)", file=sys.stderr,
+              flush=True)
+        seq = sequential_sample(fs, torch, batch, tuning, args.path_steps, args.warmup)
+        seq["batched_over_sequential"] = rb["value"] / seq["value"]
+        paths["batched"]["sequential"] = seq
     gate = None
     if args.gate_steps > 0:
         print("bench: density gate, FP32 cell+offset vs FP64, %d steps" % args.gate_steps,
