@@ -403,6 +403,25 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T& total) {
 // make the workgroup's own global stores visible to it (its waves share one CU); no
 // device-scope fence, which on this GPU writes back the whole L2.
 template <class T, class Ptr>
+__device__ T array_exclusive_scan_to(Ptr src, Ptr dst, int n, T* lds) {
+  // the same scan, reading src and writing dst (no copy of src to dst first)
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < n ? lo + per : n;
+  T sum = T(0);
+  for (int i = lo; i < hi; ++i) sum = sum + src[i];
+  T total;
+  T run = block_exclusive_scan(sum, lds, total);
+  for (int i = lo; i < hi; ++i) {
+    const T v = src[i];
+    dst[i] = run;
+    run = run + v;
+  }
+  __syncthreads();
+  return total;
+}
+
+template <class T, class Ptr>
 __device__ T array_exclusive_scan(Ptr a, int n, T* lds) {
   __syncthreads();
   const int per = (n + blockDim.x - 1) / blockDim.x;

@@ -1451,26 +1451,32 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
   const int q = static_cast<int>((*sim.step + 1ull) & 1ull);
   const int nt = se.n_tiles + se.n_tail;
-  for (int t = threadIdx.x; t < nt; t += blockDim.x) se.birth_base[t] = se.birth_cnt[t];
-  const uint32_t B = array_exclusive_scan(se.birth_base, nt, lds);
+  // thread s (s < 2) settles species s: its counters are loaded before the scan, so their
+  // latency overlaps it (nothing in this kernel writes them before they are used)
+  uint32_t n_surv = 0u, nid = 0u, n_prev = 0u;
+  if (threadIdx.x < 2) {
+    const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
+    n_surv = s.n_sorted[q];
+    nid = *s.next_id;
+    n_prev = s.n_total[q ^ 1];
+  }
+  const uint32_t B = array_exclusive_scan_to(se.birth_cnt, se.birth_base, nt, lds);
   if (threadIdx.x < 2) {
     const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
     if (threadIdx.x == 0) se.birth_base[nt] = B;
-    const uint32_t n_surv = s.n_sorted[q];
     uint32_t fit = B;
     const uint32_t room = s.cap > n_surv ? s.cap - n_surv : 0u;
     if (fit > room) {
       fit = room;
       atomicOr(sim.error, kErrCapacity);
     }
-    const uint32_t nid = *s.next_id;
     if (static_cast<unsigned long long>(nid) + fit > 0xFFFFFFFFull) {
       fit = 0xFFFFFFFFu - nid;
       atomicOr(sim.error, kErrIdOverflow);
     }
     s.fin[0] = fit;
     s.fin[1] = nid;
-    *s.psteps += static_cast<unsigned long long>(s.n_total[q ^ 1]);
+    *s.psteps += static_cast<unsigned long long>(n_prev);
     s.n_total[q] = n_surv + fit;
     *s.next_id = nid + fit;
     *s.births += fit;
