@@ -45,6 +45,10 @@ class OrcParams(ctypes.Structure):
         ("eedf_max_ev", ctypes.c_double),
         ("diag_every", ctypes.c_int32),
         ("avg_start", ctypes.c_int64),
+        ("sort_mode", ctypes.c_int32), ("birth_rank", ctypes.c_int32),
+        ("coulomb", ctypes.c_int32), ("coulomb_log", ctypes.c_double),
+        ("see_gamma", ctypes.c_double), ("see_te_ev", ctypes.c_double),
+        ("refl_e", ctypes.c_double), ("circuit_cap_f_m2", ctypes.c_double),
     ]
 
 
@@ -68,6 +72,10 @@ class OrcTallies(ctypes.Structure):
         ("births", ctypes.c_int64 * 2),
         ("collisions", (ctypes.c_int64 * 3) * 2),
         ("acc_count", ctypes.c_int64), ("eedf_samples", ctypes.c_int64),
+        ("emitted", ctypes.c_int64 * 2), ("reflected", ctypes.c_int64 * 2),
+        ("kinetic", ctypes.c_double * 2), ("field_energy", ctypes.c_double),
+        ("momentum", ctypes.c_double), ("sum_rho", ctypes.c_double),
+        ("phi0", ctypes.c_double), ("q_circuit", ctypes.c_double),
     ]
 
 
@@ -105,6 +113,11 @@ def lib():
         L.orc_stable_sort_by_cell.argtypes = [I64, P, I32, P]
         L.orc_push.argtypes = [I32, I32, I32, D, P, I64, P, P, P]
         L.orc_collide.argtypes = [P, I32, U32, I64, P, P, P]
+        L.orc_coulomb_pair.argtypes = [P, I32, I32, U32, I64, D, P, P]
+        L.orc_coulomb_pairs.argtypes = [P, I32, I32, I64, P, I64, D, P, P]
+        L.orc_emit.argtypes = [P, U32, I64, I32, P, P]
+        L.orc_circuit_solve.restype = D
+        L.orc_circuit_solve.argtypes = [P, P, D, D, P, P]
         _lib = L
     return _lib
 
@@ -113,8 +126,17 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+SORT_MODES = ("counting", "fine", "none")
+
+
 def params_from(wl, fp32_offset=False):
+    """Oracle parameters of a workload.  The array order the oracle keeps follows the
+    workload's sort mode: sorted by cell for the counting and the fine (paper) sort, input
+    order for the unsorted variant; under the fine sort, whose order inside a sorting cell
+    is not fixed, births take ids in increasing parent id."""
     p = OrcParams()
+    mode = wl.get("sort_mode", "counting")
+    assert mode in SORT_MODES, mode
     for name, _ in OrcParams._fields_:
         if name == "xsec":
             p.xsec = XSEC[wl["xsec"]]
@@ -122,6 +144,10 @@ def params_from(wl, fp32_offset=False):
             p.load = LOAD[wl["load"]]
         elif name == "fp32_offset":
             p.fp32_offset = 1 if fp32_offset else 0
+        elif name == "sort_mode":
+            p.sort_mode = 1 if mode == "none" else 0
+        elif name == "birth_rank":
+            p.birth_rank = 1 if mode == "fine" else 0
         else:
             setattr(p, name, type(getattr(p, name))(wl[name]))
     return p
@@ -261,6 +287,34 @@ class Oracle:
 
     def set_counters(self, step, next_id_e, next_id_i):
         lib().orc_set_counters(self._h, int(step), int(next_id_e), int(next_id_i))
+
+    def coulomb_pair(self, sa, sb, id_a, step, n_l, va, vb):
+        va = np.array(va, dtype=np.float64)
+        vb = np.array(vb, dtype=np.float64)
+        rc = lib().orc_coulomb_pair(self._h, sa, sb, int(id_a), int(step), float(n_l),
+                                    _ptr(va), _ptr(vb))
+        return rc, va, vb
+
+    def coulomb_pairs(self, sa, sb, ids_a, step, n_l, va, vb):
+        """va, vb: (n, 3) arrays, updated in place."""
+        ids = np.ascontiguousarray(ids_a, dtype=np.uint32)
+        assert va.flags.c_contiguous and vb.flags.c_contiguous and va.dtype == np.float64
+        lib().orc_coulomb_pairs(self._h, sa, sb, ids.size, _ptr(ids), int(step), float(n_l),
+                                _ptr(va), _ptr(vb))
+
+    def emit(self, ion_id, step, wall):
+        x = np.zeros(1)
+        v = np.zeros(3)
+        rc = lib().orc_emit(self._h, int(ion_id), int(step), int(wall), _ptr(x), _ptr(v))
+        return rc, float(x[0]), v
+
+    def circuit_solve(self, rho, vs, q):
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        phi = np.zeros(self.n_nodes)
+        ef = np.zeros(self.n_nodes)
+        phi0 = lib().orc_circuit_solve(self._h, _ptr(rho), float(vs), float(q), _ptr(phi),
+                                       _ptr(ef))
+        return phi0, phi, ef
 
     def collide(self, species, pid, step, v):
         v = np.array(v, dtype=np.float64)

@@ -43,7 +43,14 @@ struct orc_sim {
     /* grid */
     double *w[2], *rho, *phi, *ef;
     double *acc_w[2], *acc_phi, *eedf;
+    uint32_t* bparent;        /* parent id of each birth (ionisations, then emissions) */
+    int64_t* bkey_perm;
     orc_tallies t;
+    /* electrode processes and circuit */
+    uint32_t t_see, t_refl;   /* emission / reflection iff a Philox word is below these */
+    double vth_see;           /* spread of the emitted electrons' velocity components */
+    double cap_norm;          /* series capacitance in units of eps0 A / dx (0: none) */
+    double q_tot;             /* charge of the driven electrode's conductor (Q / A units) */
 };
 
 /* ------------------------------------------------------------------------------------ */
@@ -466,6 +473,14 @@ int orc_collide(const orc_sim* s, int species, uint32_t id, int64_t step, double
     }
 }
 
+/* A probability as the threshold of a 32-bit Philox word: the event happens iff the word
+   is below floor(p 2^32) (p >= 1: always, except the word 2^32 - 1). */
+static uint32_t word_threshold(double p) {
+    if (!(p > 0.0)) return 0u;
+    double t = floor(p * 4294967296.0);
+    return (t >= 4294967295.0) ? 4294967295u : (uint32_t)t;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* Simulation object                                                                     */
 /* ------------------------------------------------------------------------------------ */
@@ -508,6 +523,13 @@ orc_sim* orc_create(const orc_params* p, int64_t cap_e, int64_t cap_i) {
     s->ef = (double*)xcalloc((size_t)s->n_nodes, sizeof(double));
     s->acc_phi = (double*)xcalloc((size_t)s->n_nodes, sizeof(double));
     s->eedf = (double*)xcalloc((size_t)(p->eedf_bins > 0 ? p->eedf_bins + 1 : 1), sizeof(double));
+    s->bparent = (uint32_t*)xcalloc((size_t)cmax, sizeof(uint32_t));
+    s->bkey_perm = (int64_t*)xcalloc((size_t)cmax, sizeof(int64_t));
+    s->t_see = word_threshold(p->see_gamma);
+    s->t_refl = word_threshold(p->refl_e);
+    s->vth_see = sqrt(p->see_te_ev * QE / ME) / s->k.vunit;
+    s->cap_norm = (p->circuit_cap_f_m2 > 0.0 && !p->periodic)
+                      ? p->circuit_cap_f_m2 * s->k.dx / EPS0 : 0.0;
     return s;
 }
 
@@ -521,6 +543,7 @@ void orc_destroy(orc_sim* s) {
     free(s->tx); free(s->tvx); free(s->tvy); free(s->tvz); free(s->tid);
     free(s->flags); free(s->cell); free(s->perm);
     free(s->rho); free(s->phi); free(s->ef); free(s->acc_phi); free(s->eedf);
+    free(s->bparent); free(s->bkey_perm);
     free(s);
 }
 
@@ -555,12 +578,58 @@ static void deposit_all(orc_sim* s) {
     }
 }
 
-static void solve_at(orc_sim* s, int64_t step) {
-    for (int j = 0; j < s->n_nodes; ++j) s->rho[j] = s->w[1][j] - s->w[0][j];
+/* ------------------------------------------------------------------------------------ */
+/* Series capacitor between the source and the driven electrode (an external circuit;   */
+/* Sec. 3.5 leaves boundary conditions to the literature).  The electrode and the plate */
+/* joined to it form one conductor whose charge q changes only by the particles it      */
+/* absorbs or emits.  Its plasma-side surface charge is sigma_0 = E_0, which for the     */
+/* tridiagonal system grows with the electrode potential as sigma_0 = sigma_z + Phi_0/N  */
+/* (sigma_z: the value for Phi_0 = 0); the plate holds q - sigma_0, so                    */
+/* Phi_0 = V_s + (q - sigma_0)/C, solved for Phi_0 in closed form each step.              */
+/* ------------------------------------------------------------------------------------ */
+double orc_circuit_solve(const orc_sim* s, const double* rho, double vs, double q, double* phi,
+                         double* ef) {
+    const int N = s->p.n_cells;
+    const double C = s->cap_norm;
+    orc_solve(0, N, rho, 0.0, phi, ef);
+    double sigma_z = ef[0];
+    double phi0 = (vs + (q - sigma_z) / C) / (1.0 + 1.0 / ((double)N * C));
+    orc_solve(0, N, rho, phi0, phi, ef);
+    return phi0;
+}
+
+/* Field of step `step` from the current node weights; with `init` the circuit's charge is
+   set so that the capacitor starts uncharged.  Records the net charge and field energy. */
+static void solve_at(orc_sim* s, int64_t step, int init) {
+    double sr = 0.0;
+    for (int j = 0; j < s->n_nodes; ++j) {
+        s->rho[j] = s->w[1][j] - s->w[0][j];
+        sr += s->rho[j];
+    }
     double vl = 0.0;
     if (!s->p.periodic)
         vl = s->k.vhat_amp * sin(s->k.drive_phase_per_step * (double)step);
-    orc_solve(s->p.periodic, s->p.n_cells, s->rho, vl, s->phi, s->ef);
+    if (s->cap_norm > 0.0) {
+        if (init) {
+            orc_solve(0, s->p.n_cells, s->rho, 0.0, s->phi, s->ef);
+            /* uncharged capacitor: Phi_0 = V_s, so q = sigma_0 = sigma_z + V_s / N */
+            s->q_tot = s->ef[0] + vl / (double)s->p.n_cells;
+        }
+        vl = orc_circuit_solve(s, s->rho, vl, s->q_tot, s->phi, s->ef);
+    } else {
+        orc_solve(s->p.periodic, s->p.n_cells, s->rho, vl, s->phi, s->ef);
+    }
+    const int N = s->p.n_cells;
+    double fe = 0.0;
+    for (int j = 0; j < N; ++j) {
+        double a = s->phi[j];
+        double b = (s->p.periodic && j == N - 1) ? s->phi[0] : s->phi[j + 1];
+        fe += (a - b) * (a - b);
+    }
+    s->t.field_energy = 0.5 * fe;
+    s->t.sum_rho = sr;
+    s->t.phi0 = s->p.periodic ? 0.0 : s->phi[0];
+    s->t.q_circuit = s->q_tot;
 }
 
 /* Conversion of an FP64 position to the cell + FP32 offset layout: the offset is x - cell
@@ -623,7 +692,7 @@ int orc_load(orc_sim* s) {
         sort_species(s, sp);
     }
     deposit_all(s);
-    solve_at(s, 0);
+    solve_at(s, 0, 1);
     for (int sp = 0; sp < 2; ++sp) {
         double kap = s->k.kappa[sp];
         for (int64_t i = 0; i < s->n[sp]; ++i) {
@@ -657,13 +726,210 @@ static int is_eedf_step(const orc_sim* s, int64_t step) {
     return ((step - s->p.avg_start) % s->p.diag_every) == 0;
 }
 
-/* One PIC cycle (Sec. 2, Fig. pic_cycle): field from rho_n, push, removal at the walls,
-   MCC on the survivors, re-sort by cell, charge assignment of the new positions. */
+/* ------------------------------------------------------------------------------------ */
+/* Electrode processes (Sec. 2: if secondary electrons or reflection are featured,       */
+/* electrons are inserted at the boundaries).  Draws: counter (id, step, block, tag 0)   */
+/* under the key of the particle's own species, blocks 6-8 (the collision draws use 0-5).*/
+/* Reflection: block 6 word 0 below floor(r 2^32); the electron is mirrored in the wall   */
+/* it crossed (x -> -x or 2N - x, v_x -> -v_x).  Secondary emission: an absorbed ion's    */
+/* block 6 word 0 below floor(gamma 2^32) emits one electron: |v_x| Rayleigh-distributed  */
+/* (the flux of a Maxwellian at see_te_ev through the wall; block 7 words 0-1), v_y, v_z */
+/* normal (block 8), pointing into the box, at the distance a random fraction of one     */
+/* step's flight from the wall (block 7 words 2-3).                                      */
+/* ------------------------------------------------------------------------------------ */
+int orc_emit(const orc_sim* s, uint32_t ion_id, int64_t step, int wall, double* x, double v[3]) {
+    uint32_t b6[4], b7[4], b8[4];
+    draw(s, 1, ion_id, (uint32_t)step, 6, 0, b6);
+    if (!(b6[0] < s->t_see)) return 0;
+    draw(s, 1, ion_id, (uint32_t)step, 7, 0, b7);
+    draw(s, 1, ion_id, (uint32_t)step, 8, 0, b8);
+    double ua = orc_u53(b7[0], b7[1]);
+    double uf = orc_u53(b7[2], b7[3]);
+    double vn = s->vth_see * sqrt(-2.0 * log(1.0 - ua));
+    double z0, z1;
+    normals(b8, &z0, &z1);
+    const double N = (double)s->p.n_cells;
+    if (wall == 0) {
+        v[0] = vn;
+        *x = uf * vn;
+    } else {
+        v[0] = -vn;
+        *x = N - uf * vn;
+    }
+    v[1] = s->vth_see * z0;
+    v[2] = s->vth_see * z1;
+    if (!(*x >= 0.0 && *x < N)) return 0;
+    return 1;
+}
+
+/* Mirror an electron that crossed a wall; returns 1 if it is back inside the box. */
+static int reflect(const orc_sim* s, double* x, double* vx, int wall) {
+    const int N = s->p.n_cells;
+    if (!s->p.fp32_offset) {
+        *x = (wall == 0) ? -*x : 2.0 * (double)N - *x;
+    } else {
+        /* the same mirror on the cell + FP32 offset layout: cell c, offset f -> cell
+           -c - 1 (or 2N - c - 1), offset 1 - f */
+        int c = (int)floor(*x);
+        float f = (float)(*x - (double)c);
+        int cn = (wall == 0) ? -c - 1 : 2 * N - c - 1;
+        float fn = 1.0f - f;
+        if (fn >= 1.0f) {
+            fn = 0.0f;
+            cn += 1;
+        }
+        *x = (double)cn + (double)fn;
+    }
+    *vx = -*vx;
+    return (*x >= 0.0 && *x < (double)N);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Binary Coulomb collision of two particles of one cell (the collisions fine sorting   */
+/* makes straightforward, Sec. 3.2), after Takizuka and Abe (J. Comput. Phys. 25, 205,  */
+/* 1977): the relative velocity u = v_a - v_b is turned by an angle Theta with          */
+/* tan(Theta/2) = delta, delta normal with variance                                      */
+/*   q_a^2 q_b^2 n_L lnLambda dt / (8 pi eps0^2 m_ab^2 |u|^3)   (m_ab reduced mass),     */
+/* about a uniformly drawn azimuth Phi; both particles share the change so that the     */
+/* pair's momentum and kinetic energy are unchanged.  Draws: counter (id_a, step, block, */
+/* tag 2) under particle a's species key; like pairs blocks 0 (delta) and 1 (Phi),      */
+/* electron-ion pairs blocks 2 and 3.                                                    */
+/* ------------------------------------------------------------------------------------ */
+int orc_coulomb_pair(const orc_sim* s, int sa, int sb, uint32_t id_a, int64_t step,
+                     double n_l, double va[3], double vb[3]) {
+    const orc_consts* k = &s->k;
+    double u[3] = {va[0] - vb[0], va[1] - vb[1], va[2] - vb[2]};
+    double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (!(u2 > 0.0)) return 1;
+    double um = sqrt(u2);
+    double ma = k->mass[sa], mb = k->mass[sb];
+    double mab = ma * mb / (ma + mb);
+    double usi = um * k->vunit;
+    double var = (QE * QE) * (QE * QE) * n_l * s->p.coulomb_log * s->p.dt_s /
+                 (8.0 * (TWO_PI / 2.0) * EPS0 * EPS0 * mab * mab * usi * usi * usi);
+    uint32_t blk = (sa == sb) ? 0u : 2u;
+    uint32_t b0[4], b1[4];
+    draw(s, sa, id_a, (uint32_t)step, blk, 2, b0);
+    draw(s, sa, id_a, (uint32_t)step, blk + 1u, 2, b1);
+    double z0, z1;
+    normals(b0, &z0, &z1);
+    double delta = sqrt(var) * z0;
+    double ph = TWO_PI * orc_u53(b1[0], b1[1]);
+    double sth = 2.0 * delta / (1.0 + delta * delta);
+    double omc = 2.0 * delta * delta / (1.0 + delta * delta);
+    double cph = cos(ph), sph = sin(ph);
+    double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+    double du[3];
+    if (up > 0.0) {
+        du[0] = (u[0] / up) * u[2] * sth * cph - (u[1] / up) * um * sth * sph - u[0] * omc;
+        du[1] = (u[1] / up) * u[2] * sth * cph + (u[0] / up) * um * sth * sph - u[1] * omc;
+        du[2] = -up * sth * cph - u[2] * omc;
+    } else {
+        du[0] = u[2] * sth * cph;
+        du[1] = u[2] * sth * sph;
+        du[2] = -u[2] * omc;
+    }
+    double fa = mb / (ma + mb), fb = ma / (ma + mb);
+    for (int a = 0; a < 3; ++a) {
+        va[a] = va[a] + fa * du[a];
+        vb[a] = vb[a] - fb * du[a];
+    }
+    return 0;
+}
+
+/* The pair collision applied to n pairs (a_k, b_k) with ids id_a[k] in turn (velocities as
+   n x 3 arrays); a helper of the pins, the cycle pairs particles in coulomb_step. */
+void orc_coulomb_pairs(const orc_sim* s, int sa, int sb, int64_t n, const uint32_t* id_a,
+                       int64_t step, double n_l, double* va, double* vb) {
+    for (int64_t q = 0; q < n; ++q)
+        orc_coulomb_pair(s, sa, sb, id_a[q], step, n_l, va + 3 * q, vb + 3 * q);
+}
+
+/* Coulomb collisions of the cell-sorted survivors [0, nsurv[s]) of both species: in every
+   cell the like particles pair up in array order (first with second, third with fourth,
+   ...; an odd one out does not collide), then the k-th electron of the cell pairs with
+   its k-th ion.  n_L: the cell density of the species (like pairs) or the lower of the
+   two (electron-ion). */
+static void coulomb_step(orc_sim* s, const int64_t nsurv[2], int64_t step) {
+    const int N = s->p.n_cells;
+    const double dens = s->k.weight_per_area / s->k.dx;
+    int64_t* start[2];
+    for (int sp = 0; sp < 2; ++sp) {
+        start[sp] = (int64_t*)calloc((size_t)N + 1, sizeof(int64_t));
+        for (int64_t i = 0; i < nsurv[sp]; ++i) start[sp][(int)floor(s->x[sp][i]) + 1]++;
+        for (int c = 0; c < N; ++c) start[sp][c + 1] += start[sp][c];
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        if (!(s->p.coulomb & (sp == 0 ? ORC_COUL_EE : ORC_COUL_II))) continue;
+        for (int c = 0; c < N; ++c) {
+            int64_t a = start[sp][c], n = start[sp][c + 1] - a;
+            for (int64_t q = 0; q + 1 < n; q += 2) {
+                int64_t i = a + q, j = a + q + 1;
+                double va[3] = {s->vx[sp][i], s->vy[sp][i], s->vz[sp][i]};
+                double vb[3] = {s->vx[sp][j], s->vy[sp][j], s->vz[sp][j]};
+                orc_coulomb_pair(s, sp, sp, s->id[sp][i], step, (double)n * dens, va, vb);
+                s->vx[sp][i] = va[0]; s->vy[sp][i] = va[1]; s->vz[sp][i] = va[2];
+                s->vx[sp][j] = vb[0]; s->vy[sp][j] = vb[1]; s->vz[sp][j] = vb[2];
+            }
+        }
+    }
+    if (s->p.coulomb & ORC_COUL_EI) {
+        for (int c = 0; c < N; ++c) {
+            int64_t ae = start[0][c], ne = start[0][c + 1] - ae;
+            int64_t ai = start[1][c], ni = start[1][c + 1] - ai;
+            int64_t np = ne < ni ? ne : ni;
+            for (int64_t q = 0; q < np; ++q) {
+                int64_t i = ae + q, j = ai + q;
+                double va[3] = {s->vx[0][i], s->vy[0][i], s->vz[0][i]};
+                double vb[3] = {s->vx[1][j], s->vy[1][j], s->vz[1][j]};
+                orc_coulomb_pair(s, 0, 1, s->id[0][i], step, (double)np * dens, va, vb);
+                s->vx[0][i] = va[0]; s->vy[0][i] = va[1]; s->vz[0][i] = va[2];
+                s->vx[1][j] = vb[0]; s->vy[1][j] = vb[1]; s->vz[1][j] = vb[2];
+            }
+        }
+    }
+    if (s->p.fp32_offset)
+        for (int sp = 0; sp < 2; ++sp)
+            for (int64_t i = 0; i < nsurv[sp]; ++i) {
+                s->vx[sp][i] = (double)(float)s->vx[sp][i];
+                s->vy[sp][i] = (double)(float)s->vy[sp][i];
+                s->vz[sp][i] = (double)(float)s->vz[sp][i];
+            }
+    free(start[0]);
+    free(start[1]);
+}
+
+/* Births ordered by parent id within [lo, hi) (a stable sort of their indices). */
+struct birth_key {
+    uint32_t key;
+    int64_t idx;
+};
+static int cmp_birth_key(const void* a, const void* b) {
+    const struct birth_key* x = (const struct birth_key*)a;
+    const struct birth_key* y = (const struct birth_key*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+static void order_births_by_parent(orc_sim* s, int64_t lo, int64_t hi, int64_t* perm) {
+    int64_t n = hi - lo;
+    struct birth_key* k = (struct birth_key*)xcalloc((size_t)n, sizeof(struct birth_key));
+    for (int64_t i = 0; i < n; ++i) {
+        k[i].key = s->bparent[lo + i];
+        k[i].idx = lo + i;
+    }
+    qsort(k, (size_t)n, sizeof(struct birth_key), cmp_birth_key);
+    for (int64_t i = 0; i < n; ++i) perm[lo + i] = k[i].idx;
+    free(k);
+}
+
+/* One PIC cycle (Sec. 2, Fig. pic_cycle): field from rho_n, push, removal at the walls
+   (with electrode reflection and emission when featured), MCC on the survivors, re-sort
+   by cell, charge assignment of the new positions. */
 int orc_step(orc_sim* s) {
     const orc_params* p = &s->p;
     const orc_consts* k = &s->k;
     const int64_t step = s->t.step;
-    solve_at(s, step);
+    solve_at(s, step, 0);
     if (step >= p->avg_start) {
         for (int j = 0; j < s->n_nodes; ++j) {
             s->acc_w[0][j] += s->w[0][j];
@@ -672,13 +938,26 @@ int orc_step(orc_sim* s) {
         }
         s->t.acc_count++;
     }
-    int64_t nb = 0; /* births this step (same count for both species) */
+    int64_t nb[2] = {0, 0}; /* births this step per species */
+    int64_t nb_iz = 0;      /* ionisations (the first nb_iz births of both species) */
     int64_t nsurv[2];
+    int64_t cond0 = 0;      /* charge conducted into the driven electrode (units of Q) */
+    double mom = 0.0;
     /* electrons first: their ionisations create the births of both species */
     for (int sp = 0; sp < 2; ++sp) {
         int64_t n = s->n[sp];
+        double ak = fabs(k->kappa[sp]);
+        memcpy(s->tvx, s->vx[sp], sizeof(double) * (size_t)n); /* v_x before the push */
         orc_push(p->periodic, p->n_cells, p->fp32_offset, k->kappa[sp], s->ef, n, s->x[sp],
                  s->vx[sp], s->flags);
+        double ke = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double v0 = s->tvx[i], v1 = s->vx[sp][i];
+            double vyz = s->vy[sp][i] * s->vy[sp][i] + s->vz[sp][i] * s->vz[sp][i];
+            ke += (0.5 * (v0 * v0 + v1 * v1) + vyz) / (2.0 * ak);
+            mom += v1 / ak;
+        }
+        s->t.kinetic[sp] = ke;
         if (sp == 0 && is_eedf_step(s, step)) {
             double inv_w = (double)p->eedf_bins / p->eedf_max_ev;
             for (int64_t i = 0; i < n; ++i) {
@@ -696,9 +975,38 @@ int orc_step(orc_sim* s) {
             double v[3] = {s->vx[sp][i], s->vy[sp][i], s->vz[sp][i]};
             if (s->flags[i] != 0) {
                 int wall = s->flags[i] - 1;
+                if (sp == 0 && s->t_refl > 0u) {
+                    uint32_t b6[4];
+                    draw(s, 0, s->id[0][i], (uint32_t)step, 6, 0, b6);
+                    if (b6[0] < s->t_refl && reflect(s, &s->x[0][i], &v[0], wall)) {
+                        s->t.reflected[wall]++;
+                        s->flags[i] = 0;
+                    }
+                }
+            }
+            if (s->flags[i] != 0) {
+                int wall = s->flags[i] - 1;
                 s->t.absorbed[sp][wall]++;
                 s->t.absorbed_energy_ev[sp][wall] +=
                     k->energy_c[sp] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (wall == 0) cond0 += (sp == 0) ? -1 : 1;
+                if (sp == 1 && s->t_see > 0u) {
+                    double xe, ve[3];
+                    if (orc_emit(s, s->id[1][i], step, wall, &xe, ve)) {
+                        if (nb[0] >= s->cap[0]) return ORC_ERR_CAPACITY;
+                        if (p->fp32_offset) {
+                            xe = to_fp32_offset(xe);
+                            for (int a = 0; a < 3; ++a) ve[a] = (double)(float)ve[a];
+                        }
+                        s->bx[0][nb[0]] = xe;
+                        s->bvx[0][nb[0]] = ve[0]; s->bvy[0][nb[0]] = ve[1];
+                        s->bvz[0][nb[0]] = ve[2];
+                        s->bparent[nb[0]] = s->id[1][i];
+                        nb[0]++;
+                        s->t.emitted[wall]++;
+                        if (wall == 0) cond0 += 1;
+                    }
+                }
                 continue;
             }
             double vs[3], vi[3];
@@ -707,16 +1015,20 @@ int orc_step(orc_sim* s) {
             if (p->fp32_offset)
                 for (int a = 0; a < 3; ++a) v[a] = (double)(float)v[a];
             if (sp == 0 && ch == 3) {
+                if (nb[0] >= s->cap[0] || nb[1] >= s->cap[1]) return ORC_ERR_CAPACITY;
                 if (p->fp32_offset)
                     for (int a = 0; a < 3; ++a) {
                         vs[a] = (double)(float)vs[a];
                         vi[a] = (double)(float)vi[a];
                     }
-                s->bx[0][nb] = s->x[0][i];
-                s->bvx[0][nb] = vs[0]; s->bvy[0][nb] = vs[1]; s->bvz[0][nb] = vs[2];
-                s->bx[1][nb] = s->x[0][i];
-                s->bvx[1][nb] = vi[0]; s->bvy[1][nb] = vi[1]; s->bvz[1][nb] = vi[2];
-                nb++;
+                s->bx[0][nb[0]] = s->x[0][i];
+                s->bvx[0][nb[0]] = vs[0]; s->bvy[0][nb[0]] = vs[1]; s->bvz[0][nb[0]] = vs[2];
+                s->bparent[nb[0]] = s->id[0][i];
+                s->bx[1][nb[1]] = s->x[0][i];
+                s->bvx[1][nb[1]] = vi[0]; s->bvy[1][nb[1]] = vi[1]; s->bvz[1][nb[1]] = vi[2];
+                nb[0]++;
+                nb[1]++;
+                nb_iz++;
             }
             /* survivors are compacted in input order */
             s->x[sp][m] = s->x[sp][i];
@@ -726,24 +1038,39 @@ int orc_step(orc_sim* s) {
         }
         nsurv[sp] = m;
     }
+    s->t.momentum = mom;
+    s->q_tot += (double)cond0;
     for (int sp = 0; sp < 2; ++sp) {
-        if (nsurv[sp] + nb > s->cap[sp]) return ORC_ERR_CAPACITY;
-        if ((uint64_t)s->t.next_id[sp] + (uint64_t)nb > 4294967295ULL) return ORC_ERR_ID_OVERFLOW;
+        if (nsurv[sp] + nb[sp] > s->cap[sp]) return ORC_ERR_CAPACITY;
+        if ((uint64_t)s->t.next_id[sp] + (uint64_t)nb[sp] > 4294967295ULL)
+            return ORC_ERR_ID_OVERFLOW;
+    }
+    /* birth order: ionisations in parent order, then emissions in parent-ion order;
+       with ORC_RANK_PARENT_ID each group by increasing parent id */
+    int64_t* bperm = s->bkey_perm;
+    for (int64_t b = 0; b < nb[0]; ++b) bperm[b] = b;
+    if (p->birth_rank == ORC_RANK_PARENT_ID) {
+        order_births_by_parent(s, 0, nb_iz, bperm);
+        order_births_by_parent(s, nb_iz, nb[0], bperm);
     }
     for (int sp = 0; sp < 2; ++sp) {
         s->n[sp] = nsurv[sp];
-        sort_species(s, sp);
-        for (int64_t b = 0; b < nb; ++b) {
+        if (p->sort_mode == ORC_SORT_CELL) sort_species(s, sp);
+    }
+    if (p->coulomb && p->sort_mode == ORC_SORT_CELL) coulomb_step(s, nsurv, step);
+    for (int sp = 0; sp < 2; ++sp) {
+        for (int64_t b = 0; b < nb[sp]; ++b) {
             int64_t j = nsurv[sp] + b;
-            s->x[sp][j] = s->bx[sp][b];
-            s->vx[sp][j] = s->bvx[sp][b];
-            s->vy[sp][j] = s->bvy[sp][b];
-            s->vz[sp][j] = s->bvz[sp][b];
+            int64_t src = bperm[b]; /* the ion births follow the ionisations' order */
+            s->x[sp][j] = s->bx[sp][src];
+            s->vx[sp][j] = s->bvx[sp][src];
+            s->vy[sp][j] = s->bvy[sp][src];
+            s->vz[sp][j] = s->bvz[sp][src];
             s->id[sp][j] = s->t.next_id[sp] + (uint32_t)b;
         }
-        s->n[sp] = nsurv[sp] + nb;
-        s->t.next_id[sp] += (uint32_t)nb;
-        s->t.births[sp] += nb;
+        s->n[sp] = nsurv[sp] + nb[sp];
+        s->t.next_id[sp] += (uint32_t)nb[sp];
+        s->t.births[sp] += nb[sp];
     }
     deposit_all(s);
     s->t.step = step + 1;

@@ -41,7 +41,33 @@ typedef struct orc_params {
     double eedf_max_ev;
     int32_t diag_every;
     int64_t avg_start;
+    /* Array order after a step: ORC_SORT_CELL keeps the survivors stably sorted by cell
+       (Sec. 3.7); ORC_SORT_NONE keeps them in input order (the unsorted variant of
+       Sec. 3.2).  Births follow the survivors either way. */
+    int32_t sort_mode;
+    /* ORC_RANK_PARENT_INDEX: births take ids in the array order of their parents;
+       ORC_RANK_PARENT_ID: in increasing parent id (for a layout whose order within a
+       sorting cell is not fixed). */
+    int32_t birth_rank;
+    /* Binary Coulomb collisions between particles of one grid cell (Sec. 3.2 names them
+       as what fine sorting makes simple): bit 0 e-e, bit 1 i-i, bit 2 e-i; Coulomb
+       logarithm. */
+    int32_t coulomb;
+    double coulomb_log;
+    /* Electrode processes (Sec. 2: electrons inserted at the boundaries): each absorbed
+       ion emits a secondary electron with probability see_gamma, from a half-Maxwellian
+       at see_te_ev; an electron reaching an electrode is reflected with probability
+       refl_e. */
+    double see_gamma, see_te_ev, refl_e;
+    /* External circuit (Sec. 3.5 defers boundary conditions to the literature): a
+       capacitor of circuit_cap_f_m2 farad per electrode area in series between the source
+       and the driven electrode; 0 keeps the ideal voltage source. */
+    double circuit_cap_f_m2;
 } orc_params;
+
+enum { ORC_SORT_CELL = 0, ORC_SORT_NONE = 1 };
+enum { ORC_RANK_PARENT_INDEX = 0, ORC_RANK_PARENT_ID = 1 };
+enum { ORC_COUL_EE = 1, ORC_COUL_II = 2, ORC_COUL_EI = 4 };
 
 typedef struct orc_consts {
     double dx, weight_per_area, kappa[2], phi_scale, vunit, energy_c[2];
@@ -58,6 +84,15 @@ typedef struct orc_tallies {
     int64_t births[2];
     int64_t collisions[2][3];         /* e: elastic, excitation, ionization; i: isotropic, cx */
     int64_t acc_count, eedf_samples;
+    int64_t emitted[2];               /* secondary electrons per wall */
+    int64_t reflected[2];             /* reflected electrons per wall */
+    /* Of the last step, normalised units (energy Q^2 dx / (eps0 A), momentum
+       Q^2 dt / (eps0 A), charge Q / A): kinetic energy per species, the mean of the
+       values before and after the push (velocities before the collisions); field energy
+       1/2 sum over cells of (Phi_j - Phi_j+1)^2; x-momentum sum v_x / |kappa_s| after the
+       push; sum of the net node charge; the driven electrode's potential; the charge of
+       the driven electrode's conductor (electrode surface + capacitor plate). */
+    double kinetic[2], field_energy, momentum, sum_rho, phi0, q_circuit;
 } orc_tallies;
 
 typedef struct orc_sim orc_sim;
@@ -94,6 +129,21 @@ void orc_push(int periodic, int n_cells, int fp32_offset, double kappa, const do
    ionisation the secondary electron's and the new ion's velocities are written. */
 int orc_collide(const orc_sim* s, int species, uint32_t id, int64_t step, double v[3],
                 double v_sec[3], double v_ion[3]);
+/* One binary Coulomb collision of a pair (species sa, sb; particle a's id and step key
+   the draw); velocities updated in place; n_l_m3 the density that sets the rate.
+   Returns 0, or 1 if the pair did not collide (zero relative velocity). */
+int orc_coulomb_pair(const orc_sim* s, int sa, int sb, uint32_t id_a, int64_t step,
+                     double n_l_m3, double va[3], double vb[3]);
+void orc_coulomb_pairs(const orc_sim* s, int sa, int sb, int64_t n, const uint32_t* id_a,
+                       int64_t step, double n_l_m3, double* va, double* vb);
+/* Secondary electron of an ion absorbed at `wall` (0 at x = 0, 1 at x = N): returns 1 and
+   its position and velocity if one is emitted. */
+int orc_emit(const orc_sim* s, uint32_t ion_id, int64_t step, int wall, double* x,
+             double v[3]);
+/* Driven-electrode potential of the series-capacitor circuit for a node charge rho
+   (normalised), source value vs and conductor charge q; phi and E are the solution. */
+double orc_circuit_solve(const orc_sim* s, const double* rho, double vs, double q, double* phi,
+                         double* efield);
 
 #ifdef __cplusplus
 }

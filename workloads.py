@@ -44,6 +44,13 @@ def base(**kw):
         sigma_const_m2=0.0, eps_cap_ev=100.0, seed=0, discharge=0, load="random",
         langmuir_amp_cells=0.0, langmuir_mode=1, eedf_bins=120, eedf_max_ev=60.0,
         diag_every=10, avg_start=0, steps=10,
+        # array order kept by the step: "counting" (stable counting sort by cell),
+        # "fine" (the paper's fixed-capacity sorting cells), "none" (unsorted)
+        sort_mode="counting", grid_points_per_sort_cell=3, sort_cell_capacity=0,
+        # binary Coulomb collisions in a cell: bit 0 e-e, bit 1 i-i, bit 2 e-i
+        coulomb=0, coulomb_log=10.0,
+        # electrode processes and the series capacitor of the driven electrode
+        see_gamma=0.0, see_te_ev=2.0, refl_e=0.0, circuit_cap_f_m2=0.0,
     )
     d.update(kw)
     return d
