@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define FSPIC_ABI_VERSION 1u
+#define FSPIC_ABI_VERSION 2u
 
 enum pic_status {
   PIC_OK = 0,
@@ -42,7 +42,9 @@ enum pic_status {
   PIC_ERR_NONFINITE = -4,   /* a particle position became non-finite (deferred) */
   PIC_ERR_ID_OVERFLOW = -5, /* particle ids would exceed 2^32 - 1 (deferred) */
   PIC_ERR_STATE = -6,       /* call out of order (e.g. step before init) */
-  PIC_ERR_WORKSPACE = -7    /* workspace smaller than pic_workspace_bytes() */
+  PIC_ERR_WORKSPACE = -7,   /* workspace smaller than pic_workspace_bytes() */
+  PIC_ERR_CORRUPT = -8      /* inconsistent device state: a kernel refused an index out of
+                               range (deferred); the particle state is no longer valid */
 };
 
 enum pic_precision {
@@ -75,13 +77,40 @@ typedef struct pic_config {
   uint32_t diag_every;       /* EEDF sampled every diag_every steps from avg_start_step */
   uint32_t reserved0;
   uint64_t avg_start_step;   /* time averages accumulate from this step on */
-  /* tuning: changes speed only (results differ at most by floating-point summation
-     order of the deposit); 0 selects the default */
+  /* tuning: changes speed only (the results are bit for bit the same: charge is summed
+     in fixed point and every other sum in a fixed order); 0 selects the default */
   uint32_t cells_per_tile[2];/* cells owned by one workgroup, per species */
   uint32_t window[2];        /* cells a particle may move per step on the fast sort path */
   uint32_t tail_groups;      /* workgroups per species that take the births tail */
   uint32_t far_capacity;     /* entries of the per-species far-mover list */
+  /* --- optional physics and the array order (0 everywhere keeps the plain cycle) --- */
+  uint32_t sort_mode;        /* pic_sort: array order kept by the step */
+  uint32_t coulomb;          /* binary Coulomb collisions between particles of one grid cell
+                                (what fine sorting makes simple, Sec. 3.2): bit 0 e-e,
+                                bit 1 i-i, bit 2 e-i; needs PIC_SORT_COUNTING */
+  double coulomb_log;        /* Coulomb logarithm */
+  double see_gamma;          /* secondary electrons per ion absorbed at an electrode (Sec. 2:
+                                electrons inserted at the boundaries), at most 1 */
+  double see_te_ev;          /* temperature of the emitted electrons [eV] */
+  double refl_e;             /* probability that an electron reaching an electrode is
+                                reflected */
+  double circuit_cap_f_m2;   /* series capacitor between the source and the driven electrode
+                                [F per m^2 of electrode]; 0: ideal voltage source */
+  uint32_t sort_cell_cells;  /* PIC_SORT_FINE: grid cells per sorting cell (N_gc - 1) */
+  uint32_t sort_cell_capacity; /* PIC_SORT_FINE: particle slots per sorting cell (N_max);
+                                0: derived from the load */
 } pic_config;
+
+enum pic_sort {
+  PIC_SORT_COUNTING = 0, /* stable counting sort by cell into a second buffer (Sec. 3.7's
+                            result, canonical order) */
+  PIC_SORT_NONE = 1,     /* unsorted: survivors keep their order, the deposit adds straight
+                            into the node array (the unsorted GPU variant of Sec. 3.2) */
+  PIC_SORT_FINE = 2      /* the paper's in-place sort into fixed-capacity sorting cells
+                            (Sec. 3.2 data structure, Sec. 3.7 steps 1a/1b, 2 and 3); the
+                            order inside a sorting cell is not fixed, so births take their
+                            ids in increasing parent id */
+};
 
 /* Normalised constants the library derives from a pic_config (Sec. 3.3). */
 typedef struct pic_derived {
@@ -104,6 +133,23 @@ typedef struct pic_diag {
   uint64_t particle_steps[2];       /* particles pushed, summed over all steps so far */
   uint32_t error_flags;
   uint32_t reserved0;
+  /* Energies and momentum (Sec. 2: averaging gives the macroscopic values), normalised
+     units of Sec. 3.3 per electrode area: energy (eW/A)^2 dx/eps0, momentum
+     (eW/A)^2 dt/eps0, charge eW/A.  kinetic and momentum are taken on the steps the EEDF
+     is sampled on (diag_every from avg_start_step); energy_step says which. */
+  double kinetic[2];                /* sum over particles of (v_x^2 before + v_x^2 after the
+                                       push)/2 + v_y^2 + v_z^2, over 2 |kappa_s| */
+  double momentum;                  /* sum_s sum_i v_x(after the push) / |kappa_s| */
+  uint64_t energy_step;
+  double field_energy;              /* last solve: 1/2 sum over cells (Phi_j - Phi_j+1)^2 */
+  double sum_rho;                   /* last solve: sum over nodes of w_i - w_e */
+  double phi_driven_v;              /* last solve: potential of the driven electrode [V] */
+  double circuit_charge;            /* charge of the driven electrode's conductor */
+  uint64_t emitted[2];              /* secondary electrons per wall, summed over steps */
+  uint64_t reflected[2];            /* reflected electrons per wall, summed over steps */
+  double* eedf;                     /* in: caller buffer for the EEDF counts, or NULL */
+  uint32_t eedf_len;                /* in: its length; out: entries written (<= bins + 1) */
+  uint32_t reserved1;
 } pic_diag;
 
 /* Host-side particle state of one discharge, caller-allocated.  Fill the arrays of the
@@ -179,7 +225,9 @@ int pic_set_state(pic_sim* sim, int discharge, const pic_state* st);  /* syncs *
    pic_profile(sim, 1|0) turns it on or off and resets the totals; pic_profile_read
    waits for the recorded steps and returns, per phase, the summed milliseconds and the
    number of steps.  Phases: 0 combine, 1 solve, 2 hist, 3 scan (two kernels: from the
-   start of the first to the end of the second), 4 main, 5 collide, 6 finalize.
+   start of the first to the end of the second), 4 main, 5 collide, 6 finalize (two
+   kernels), 7 coulomb (zero when no discharge has Coulomb collisions), 8 fine_sort (the
+   three steps of PIC_SORT_FINE; zero without it).
    Errors: PIC_ERR_STATE (null sim), PIC_ERR_ARG (null outputs), PIC_ERR_DEVICE. */
 int pic_profile(pic_sim* sim, int enable);
 int pic_profile_read(pic_sim* sim, double* ms_total, uint64_t* launches, int n_phases);

@@ -19,14 +19,16 @@ except ImportError:  # pragma: no cover - torch is part of the environment
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfspic.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 PIC_FP64, PIC_FP32_OFFSET = 0, 1
 XSEC = {"none": 0, "const_e_elastic": 1, "ar_like": 2}
 LOAD = {"random": 0, "quiet_langmuir": 1}
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_CAPACITY", -3: "PIC_ERR_DEVICE",
           -4: "PIC_ERR_NONFINITE", -5: "PIC_ERR_ID_OVERFLOW", -6: "PIC_ERR_STATE",
-          -7: "PIC_ERR_WORKSPACE"}
-PHASES = ("combine", "solve", "hist", "scan", "main", "collide", "finalize")
+          -7: "PIC_ERR_WORKSPACE", -8: "PIC_ERR_CORRUPT"}
+SORT = {"counting": 0, "none": 1, "fine": 2}
+PHASES = ("combine", "solve", "hist", "scan", "main", "collide", "finalize", "coulomb",
+          "fine_sort")
 
 U32, U64, I32, F64, P = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double,
                          ctypes.c_void_p)
@@ -49,6 +51,9 @@ class PicConfig(ctypes.Structure):
         ("avg_start_step", U64),
         ("cells_per_tile", U32 * 2), ("window", U32 * 2), ("tail_groups", U32),
         ("far_capacity", U32),
+        ("sort_mode", U32), ("coulomb", U32), ("coulomb_log", F64), ("see_gamma", F64),
+        ("see_te_ev", F64), ("refl_e", F64), ("circuit_cap_f_m2", F64),
+        ("sort_cell_cells", U32), ("sort_cell_capacity", U32),
     ]
 
 
@@ -70,6 +75,10 @@ class PicDiag(ctypes.Structure):
         ("acc_count", U64), ("eedf_samples", U64),
         ("surface_charge", F64 * 2), ("particle_steps", U64 * 2), ("error_flags", U32),
         ("reserved0", U32),
+        ("kinetic", F64 * 2), ("momentum", F64), ("energy_step", U64),
+        ("field_energy", F64), ("sum_rho", F64), ("phi_driven_v", F64),
+        ("circuit_charge", F64), ("emitted", U64 * 2), ("reflected", U64 * 2),
+        ("eedf", ctypes.POINTER(F64)), ("eedf_len", U32), ("reserved1", U32),
     ]
 
 
@@ -163,6 +172,15 @@ def make_config(wl, precision="fp32_offset", cap_factor=1.5, tuning=None):
             getattr(c, k)[0], getattr(c, k)[1] = int(v[0]), int(v[1])
     c.tail_groups = int(t.get("tail_groups", 0))
     c.far_capacity = int(t.get("far_capacity", 0))
+    c.sort_mode = SORT[wl.get("sort_mode", "counting")]
+    c.coulomb = int(wl.get("coulomb", 0))
+    c.coulomb_log = float(wl.get("coulomb_log", 10.0))
+    c.see_gamma = float(wl.get("see_gamma", 0.0))
+    c.see_te_ev = float(wl.get("see_te_ev", 2.0))
+    c.refl_e = float(wl.get("refl_e", 0.0))
+    c.circuit_cap_f_m2 = float(wl.get("circuit_cap_f_m2", 0.0))
+    c.sort_cell_cells = max(0, int(wl.get("grid_points_per_sort_cell", 3)) - 1)
+    c.sort_cell_capacity = int(wl.get("sort_cell_capacity", 0))
     return c
 
 
@@ -201,12 +219,14 @@ class Simulation:
         self.cfgs = [make_config(w, precision, cap_factor, t) for w, t in zip(wls, tunings)]
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.bytes = workspace_bytes(self.cfgs)
-        self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
         arr = (PicConfig * len(self.cfgs))(*self.cfgs)
         h = P()
+        self.static_workspace = False
+        self.bytes = workspace_bytes(self.cfgs)
+        self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
         _check("pic_init", lib().pic_init(arr, len(self.cfgs), P(self.workspace.data_ptr()),
-                                          self.bytes, P(self.stream.cuda_stream), ctypes.byref(h)))
+                                          self.bytes, P(self.stream.cuda_stream),
+                                          ctypes.byref(h)))
         self._h = h
         self.derived = [derive(c) for c in self.cfgs]
 
@@ -263,9 +283,18 @@ class Simulation:
         self._call("pic_density", d, q, int(kind), _ptr(out), out.size)
         return out
 
-    def diagnostics(self, d=0):
+    def diagnostics(self, d=0, eedf=False):
+        """pic_diag of discharge d; with eedf=True the EEDF counts come back in the same
+        call, as the array attribute ``eedf_counts``."""
         g = PicDiag()
+        buf = None
+        if eedf:
+            buf = np.zeros(self.workloads[d]["eedf_bins"] + 1)
+            g.eedf = buf.ctypes.data_as(ctypes.POINTER(F64))
+            g.eedf_len = buf.size
         self._call("pic_diagnostics", d, ctypes.byref(g))
+        if buf is not None:
+            g.eedf_counts = buf[:g.eedf_len].copy()
         return g
 
     def get_state(self, d=0):

@@ -9,9 +9,9 @@ for every discharge at once, one factor at a time:
 * then electron D ×{1, 1/2}.
 
 It keeps the fastest. Tile geometry changes speed only: the output order is the stable
-sort by cell whatever the tiles, and results differ at most by the summation order of
-the deposit. A candidate the library rejects, or one that overflows a list while it is
-timed, is skipped.
+sort by cell whatever the tiles, and the charge is summed in fixed point, so the results
+are bit for bit the same. A candidate the library rejects, or one that overflows a list
+while it is timed, is skipped.
 
 Each candidate is timed as steps replayed from a HIP graph, after warm-up steps, from
 the seeded load, between HIP events on the simulation's stream. The choice can be cached

@@ -17,7 +17,7 @@ namespace {
 
 thread_local std::string g_init_error;
 
-constexpr int kPhases = 7;
+constexpr int kPhases = 9;
 constexpr int kRing = 32;  // steps whose phase events are in flight before they are read
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -116,7 +116,16 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
     D.E64 = cv.take<double>(nn);
     D.E32 = cv.take<float>(nn);
     D.acc_phi = cv.take<double>(nn);
-    D.scratch = cv.take<double>(nn);
+    D.dstat = cv.take<double>(DS_N);
+    D.energy_step = cv.take<unsigned long long>(1);
+    D.cap_norm = circuit_cap_norm(c, k);
+    D.coulomb = static_cast<int32_t>(c.coulomb);
+    coulomb_coefficients(c, D.coul_coef);
+    D.coul_dens = k.weight_per_area / k.dx;
+    D.vunit = k.vunit;
+    D.mfrac_e = ion_mass(c) / (electron_mass() + ion_mass(c));
+    D.mfrac_i = electron_mass() / (electron_mass() + ion_mass(c));
+    if (c.coulomb) pl->li.coulomb = true;
     D.acc_count = cv.take<unsigned long long>(1);
     D.eedf_samples = cv.take<unsigned long long>(1);
     D.eedf_bins = static_cast<int>(c.eedf_bins);
@@ -129,10 +138,23 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
     for (int s = 0; s < 2; ++s) {
       SpeciesDev& S = pl->sp[2 * d + s];
       const TileChoice& tc = pl->tiles[2 * d + s];
-      const uint32_t cap = static_cast<uint32_t>(s == 0 ? c.capacity_e : c.capacity_i);
+      uint32_t cap = static_cast<uint32_t>(s == 0 ? c.capacity_e : c.capacity_i);
+      if (c.sort_mode == PIC_SORT_FINE) {
+        // every sorting cell's slots, and the contiguous arrays of the load / set_state
+        const uint64_t slots = static_cast<uint64_t>(tc.n_tiles) * static_cast<uint64_t>(tc.nmax);
+        if (tc.nmax > kMaxFineSlots || slots >= (1ull << 26)) {
+          *why = "discharge " + std::to_string(d) + ": fine sort needs " + std::to_string(slots) +
+                 " slots (sorting cells x sort_cell_capacity): must be < 2^26, at most 65536 "
+                 "per sorting cell";
+          return PIC_ERR_ARG;
+        }
+        cap = std::max<uint32_t>(cap, static_cast<uint32_t>(slots));
+        pl->li.fine = true;
+      }
       max_cap = std::max(max_cap, static_cast<int>(cap));
       S.ds = d;
       S.sp = s;
+      S.mode = static_cast<int32_t>(c.sort_mode);
       S.n_cells = N;
       S.periodic = static_cast<int>(c.periodic);
       S.C = tc.C;
@@ -174,6 +196,21 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
           S.stage[b][F_ID] = nullptr;
         }
       }
+      for (int f = 0; f < 6; ++f) S.fine[f] = nullptr;
+      S.nmax = static_cast<uint32_t>(tc.nmax);
+      S.fcnt = S.flv = S.fpid = S.fpid_list = nullptr;
+      if (c.sort_mode == PIC_SORT_FINE) {
+        for (int f = 0; f < 6; ++f) {
+          if (!fp32 && f == 1) continue;
+          S.fine[f] = cv.take<char>(((fp32 || f == F_ID) ? 4 : 8) * cap1);
+        }
+        S.fcnt = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles));
+        S.flv = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles));
+        if (s == 0) {
+          S.fpid = cv.take<uint32_t>(cap);
+          S.fpid_list = cv.take<uint32_t>(cap);
+        }
+      }
       S.n_total = cv.take<uint32_t>(2);
       S.n_sorted = cv.take<uint32_t>(2);
       S.next_id = cv.take<uint32_t>(1);
@@ -182,8 +219,8 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.tilerel = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * kWaves * tc.W);
       S.thist = cv.take<uint32_t>(static_cast<size_t>(tc.n_tail) * kWaves * N);
       S.trel = cv.take<uint32_t>(static_cast<size_t>(tc.n_tail) * kWaves * N);
-      S.partial = cv.take<char>(rs * static_cast<size_t>(tc.n_tiles) * (tc.W + 1));
-      S.far_w = cv.take<double>(nn);
+      S.partial = cv.take<unsigned long long>(static_cast<size_t>(tc.n_tiles) * (tc.W + 1));
+      S.far_w = cv.take<unsigned long long>(nn);
       S.far_count = cv.take<uint32_t>(1);
       S.far_list = cv.take<uint4>(S.far_cap);
       S.far_grouped = cv.take<uint4>(S.far_cap);
@@ -205,8 +242,42 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.absorbed_energy = cv.take<double>(2);
       S.births = cv.take<unsigned long long>(1);
       S.collisions = cv.take<unsigned long long>(3);
-      S.ke_sum = cv.take<double>(4);
+      S.emitted = cv.take<unsigned long long>(2);
+      S.reflected = cv.take<unsigned long long>(2);
       S.psteps = cv.take<unsigned long long>(1);
+      S.tstats = cv.take<TileStats>(static_cast<size_t>(ntt));
+      S.t_refl = s == 0 ? word_threshold(c.refl_e) : 0u;
+      S.t_see = s == 1 ? word_threshold(c.see_gamma) : 0u;
+      S.vth_see = see_spread(c, k);
+      for (int f = 0; f < 6; ++f) S.em_stage[f] = nullptr;
+      S.ab_list = nullptr;
+      S.ab_cnt = S.em_cnt = S.em_lo = S.em_base = nullptr;
+      if (S.t_see) {
+        pl->li.emission = true;
+        S.ab_list = cv.take<uint2>(cap);
+        // emitted electrons wait at their parent ion's index: electron records, cap_i long
+        if (fp32) {
+          S.em_stage[F32_CELL] = cv.take<int>(cap);
+          S.em_stage[F32_OFF] = cv.take<float>(cap);
+        } else {
+          S.em_stage[F64_X] = cv.take<double>(cap);
+        }
+        for (int f = F_VX; f <= F_VZ; ++f) S.em_stage[f] = cv.take<char>(rs * cap);
+        S.ab_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
+        S.em_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
+        S.em_lo = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
+        S.em_base = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves + 1);
+      }
+      {
+        // fixed-point deposit: a node's weight never exceeds the species' capacity, so
+        // 2^shift (cap + 1) < 2^63 keeps every sum in 64 bits; at most 52 bits of fraction
+        int bits = 0;
+        while ((uint64_t{1} << bits) <= static_cast<uint64_t>(cap) + 1) ++bits;
+        const int shift = std::min(52, 63 - bits);
+        S.dep_one = uint64_t{1} << shift;
+        S.dep_scale = std::ldexp(1.0, shift);
+        S.dep_inv = std::ldexp(1.0, -shift);
+      }
       S.kappa = k.kappa[s];
       S.kappa_f = static_cast<float>(k.kappa[s]);
       S.t0 = k.t0[s];
@@ -254,6 +325,8 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   for (int i = 0; i < 2 * n; ++i) {
     for (int j = 0; j < pl->sp[i].n_nodes; j += kCombineNodes)
       pl->node_table.push_back(make_int2(i, j));
+    // no per-cell offsets when unsorted or sorted in place
+    if (pl->sp[i].mode == kModeNone || pl->sp[i].mode == kModeFine) continue;
     for (int c = 0; c < pl->sp[i].n_cells; c += kScanCells)
       pl->cell_table.push_back(make_int2(i, c));
   }
@@ -302,6 +375,10 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
 
 }  // namespace
 
+namespace fspic {
+void set_init_error(const std::string& msg) { g_init_error = msg; }
+}  // namespace fspic
+
 struct pic_sim {
   Plan pl;
   hipStream_t stream = nullptr;
@@ -341,7 +418,8 @@ static int launch_check(pic_sim* sim, const char* what) {
 static int map_error_bits(uint32_t bits) {
   if (bits & kErrIdOverflow) return PIC_ERR_ID_OVERFLOW;
   if (bits & (kErrCapacity | kErrFarOverflow | kErrFarGroup)) return PIC_ERR_CAPACITY;
-  if (bits & kErrState) return PIC_ERR_NONFINITE;
+  if (bits & kErrNonfinite) return PIC_ERR_NONFINITE;
+  if (bits & kErrState) return PIC_ERR_CORRUPT;
   return PIC_OK;
 }
 
@@ -350,8 +428,15 @@ static const char* error_text(uint32_t bits) {
   if (bits & kErrCapacity) return "births did not fit the particle capacity";
   if (bits & kErrFarOverflow) return "far-mover list overflow (raise far_capacity / window)";
   if (bits & kErrFarGroup) return "too many far movers into one cell (raise window)";
-  if (bits & kErrState) return "invalid particle position or index refused";
+  if (bits & kErrNonfinite) return "a particle position was not finite or not in a cell";
+  if (bits & kErrState) return "inconsistent device state: an index out of range was refused";
   return "";
+}
+
+// deferred device errors that still leave the host copies readable
+static bool readable(int rc) {
+  return rc == PIC_OK || rc == PIC_ERR_CAPACITY || rc == PIC_ERR_ID_OVERFLOW ||
+         rc == PIC_ERR_NONFINITE || rc == PIC_ERR_CORRUPT;
 }
 
 extern "C" int pic_workspace_bytes(const pic_config* cfgs, int n, size_t* bytes) {
@@ -405,7 +490,10 @@ static int step_once(pic_sim* sim, hipStream_t st) {
     launch_scan(li, d, st);
     launch_main(li, d, st);
     launch_collide(li, d, st);
+    if (li.coulomb) launch_coulomb(li, d, st);
+    if (li.fine) launch_fine_sort(li, d, st);
     launch_finalize(li, d, st);
+    if (li.fine) launch_fine_births(li, d, st);
     return launch_check(sim, "step launch");
   }
   if (sim->ring_used == kRing) {
@@ -419,7 +507,20 @@ static int step_once(pic_sim* sim, hipStream_t st) {
   launch_scan(li, d, st, ev[6], ev[7]);
   launch_main(li, d, st, ev[8], ev[9]);
   launch_collide(li, d, st, ev[10], ev[11]);
+  if (li.coulomb) {
+    launch_coulomb(li, d, st, ev[14], ev[15]);
+  } else {
+    HIPCHECK(sim, hipEventRecord(ev[14], st));
+    HIPCHECK(sim, hipEventRecord(ev[15], st));
+  }
+  if (li.fine) {
+    launch_fine_sort(li, d, st, ev[16], ev[17]);
+  } else {
+    HIPCHECK(sim, hipEventRecord(ev[16], st));
+    HIPCHECK(sim, hipEventRecord(ev[17], st));
+  }
   launch_finalize(li, d, st, ev[12], ev[13]);
+  if (li.fine) launch_fine_births(li, d, st);
   sim->ring_used += 1;
   return launch_check(sim, "step launch");
 }
@@ -466,7 +567,7 @@ extern "C" int pic_init(const pic_config* cfgs, int n, void* d_workspace, size_t
       return fail(PIC_ERR_DEVICE);                                          \
     }                                                                       \
   } while (0)
-  INITCHECK(hipMemsetAsync(sim->ws, 0, pl.bytes, st));
+  launch_zero(sim->ws, pl.bytes, st);  // pl.bytes is a multiple of 256
   INITCHECK(hipMemcpyAsync(pl.d_ds, pl.ds.data(), sizeof(DischargeDev) * pl.ds.size(),
                            hipMemcpyHostToDevice, st));
   INITCHECK(hipMemcpyAsync(pl.d_sp, pl.sp.data(), sizeof(SpeciesDev) * pl.sp.size(),
@@ -487,6 +588,7 @@ extern "C" int pic_init(const pic_config* cfgs, int n, void* d_workspace, size_t
     INITCHECK(hipMemcpyAsync(S.n_total + 1, &S.n_init, sizeof(uint32_t), hipMemcpyHostToDevice, st));
   launch_load(pl.li, pl.d_sim, 1, st);
   launch_general_sort(pl.li, pl.d_sim, 1, 0, st);
+  if (pl.li.fine) launch_fine_scatter(pl.li, pl.d_sim, 0, st);
   launch_deposit_tiles(pl.li, pl.d_sim, -1, st);
   launch_combine(pl.li, pl.d_sim, st);
   launch_solve(pl.li, pl.d_sim, 1, st);
@@ -602,9 +704,7 @@ extern "C" int pic_grid(pic_sim* sim, int d, int what, double* out, size_t n_out
   const size_t need = what == 7 ? static_cast<size_t>(D.eedf_bins) + 1 : D.n_nodes;
   if (n_out < need) return PIC_ERR_ARG;
   int rc = pic_sync(sim);
-  if (rc != PIC_OK && rc != PIC_ERR_CAPACITY && rc != PIC_ERR_ID_OVERFLOW &&
-      rc != PIC_ERR_NONFINITE)
-    return rc;
+  if (!readable(rc)) return rc;
   const int sticky = rc;
   if (what <= 1) {
     rc = refresh_weights(sim);
@@ -639,9 +739,7 @@ extern "C" int pic_density(pic_sim* sim, int d, int quantity, int kind, double* 
   if (n_out < nn) return PIC_ERR_ARG;
   const int what = kind == 0 ? quantity : 4 + quantity;
   int rc = pic_grid(sim, d, what, out, n_out);
-  if (rc != PIC_OK && rc != PIC_ERR_CAPACITY && rc != PIC_ERR_ID_OVERFLOW &&
-      rc != PIC_ERR_NONFINITE)
-    return rc;
+  if (!readable(rc)) return rc;
   double norm = 1.0;
   if (kind == 1) {
     unsigned long long c = 0;
@@ -668,6 +766,8 @@ extern "C" int pic_diagnostics(pic_sim* sim, int d, pic_diag* out) {
   if (d < 0 || d >= sim->pl.li.n_ds || !out) return PIC_ERR_ARG;
   const int sticky = pic_sync(sim);
   if (sticky == PIC_ERR_DEVICE) return sticky;
+  double* const eedf_out = out->eedf;
+  const uint32_t eedf_cap = out->eedf_len;
   std::memset(out, 0, sizeof(*out));
   int rc;
   const uint64_t step = device_step(sim, &rc);
@@ -699,6 +799,33 @@ extern "C" int pic_diagnostics(pic_sim* sim, int d, pic_diag* out) {
     }
     out->births[s] = bi;
     for (int c = 0; c < 3; ++c) out->collisions[s][c] = co[c];
+    unsigned long long em[2] = {0, 0}, rf[2] = {0, 0};
+    if ((rc = d2h(sim, em, S.emitted, 2)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, rf, S.reflected, 2)) != PIC_OK) return rc;
+    for (int w = 0; w < 2; ++w) {
+      out->emitted[w] += em[w];
+      out->reflected[w] += rf[w];
+    }
+  }
+  double ds[DS_N] = {};
+  unsigned long long est = 0;
+  if ((rc = d2h(sim, ds, D.dstat, DS_N)) != PIC_OK) return rc;
+  if ((rc = d2h(sim, &est, D.energy_step, 1)) != PIC_OK) return rc;
+  out->kinetic[0] = ds[DS_KIN_E];
+  out->kinetic[1] = ds[DS_KIN_I];
+  out->momentum = ds[DS_MOM];
+  out->energy_step = est;
+  out->field_energy = ds[DS_FIELD];
+  out->sum_rho = ds[DS_SUM_RHO];
+  out->phi_driven_v = ds[DS_PHI0] * sim->pl.der[d].phi_scale;
+  out->circuit_charge = ds[DS_Q];
+  out->eedf = eedf_out;
+  if (eedf_out && eedf_cap > 0) {
+    const size_t n = std::min<size_t>(eedf_cap, static_cast<size_t>(D.eedf_bins) + 1);
+    std::vector<unsigned long long> tmp(n);
+    if ((rc = d2h(sim, tmp.data(), D.eedf, n)) != PIC_OK) return rc;
+    for (size_t i = 0; i < n; ++i) eedf_out[i] = static_cast<double>(tmp[i]);
+    out->eedf_len = static_cast<uint32_t>(n);
   }
   unsigned long long ac = 0, es = 0;
   if ((rc = d2h(sim, &ac, D.acc_count, 1)) != PIC_OK) return rc;
@@ -712,6 +839,51 @@ extern "C" int pic_diagnostics(pic_sim* sim, int d, pic_diag* out) {
   out->surface_charge[1] = D.periodic ? 0.0 : -en;
   out->error_flags = sim->sticky;
   return sticky;
+}
+
+// Host copy of a fine-sorted species: the slots of every sorting cell, compacted in
+// sorting-cell order.
+template <class T>
+static int fine_gather(pic_sim* sim, const SpeciesDev& S, const void* dev, T* host,
+                       const std::vector<uint32_t>& cnt) {
+  if (!host) return PIC_OK;
+  std::vector<T> all(static_cast<size_t>(S.n_tiles) * S.nmax);
+  int rc = d2h(sim, all.data(), static_cast<const T*>(dev), all.size());
+  if (rc != PIC_OK) return rc;
+  size_t o = 0;
+  for (int k = 0; k < S.n_tiles; ++k) {
+    const T* src = all.data() + static_cast<size_t>(k) * S.nmax;
+    std::copy(src, src + std::min(cnt[k], S.nmax), host + o);
+    o += std::min(cnt[k], S.nmax);
+  }
+  return PIC_OK;
+}
+
+static int fine_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, pic_state* st,
+                              int s) {
+  std::vector<uint32_t> cnt(S.n_tiles);
+  int rc = d2h(sim, cnt.data(), S.fcnt, cnt.size());
+  if (rc != PIC_OK) return rc;
+  uint64_t n = 0;
+  for (uint32_t c : cnt) n += std::min(c, S.nmax);
+  if (n != st->n[s]) {
+    sim->err = "pic_get_state: sorting-cell counts disagree with the particle count";
+    return PIC_ERR_CORRUPT;
+  }
+  void* const* f = S.fine;
+  if (fp32) {
+    if ((rc = fine_gather(sim, S, f[F32_CELL], st->cell[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F32_OFF], st->off[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VX], st->vxf[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VY], st->vyf[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VZ], st->vzf[s], cnt))) return rc;
+  } else {
+    if ((rc = fine_gather(sim, S, f[F64_X], st->x[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VX], st->vx[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VY], st->vy[s], cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VZ], st->vz[s], cnt))) return rc;
+  }
+  return fine_gather(sim, S, f[F_ID], st->id[s], cnt);
 }
 
 extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
@@ -738,6 +910,13 @@ extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
     if (nt > st->capacity[s]) {
       sim->err = "pic_get_state: host arrays smaller than the particle count";
       return PIC_ERR_CAPACITY;
+    }
+    if (S.mode == kModeFine) {
+      // sorting cells one after the other, each its fcnt particles
+      st->n_sorted[s] = nt;
+      if ((rc = fine_state_to_host(sim, S, fp32, st, s)) != PIC_OK) return rc;
+      if (st->w[s] && (rc = d2h(sim, st->w[s], D.w[s], D.n_nodes))) return rc;
+      continue;
     }
     void* const* f = S.fld[p];
     if (fp32) {
@@ -773,10 +952,15 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
   const bool fp32 = sim->pl.li.fp32;
   const DischargeDev& D = sim->pl.ds[d];
   const int N = D.n_cells;
+  // a fine-sorted discharge is rebuilt from a cell sort of the whole state
+  const bool fine = sim->pl.sp[2 * d].mode == kModeFine || sim->pl.sp[2 * d + 1].mode == kModeFine;
+  const bool sort_all = st->sort_all || fine;
   // validate on the host before anything is uploaded
   for (int s = 0; s < 2; ++s) {
     const SpeciesDev& S = sim->pl.sp[2 * d + s];
-    const uint64_t n = st->n[s], ns = st->sort_all ? 0 : st->n_sorted[s];
+    // an unsorted species keeps any order: no sorted prefix to check
+    const uint64_t n = st->n[s],
+                   ns = (sort_all || S.mode == kModeNone) ? 0 : st->n_sorted[s];
     if (n > S.cap || ns > n) {
       sim->err = "pic_set_state: counts exceed capacity";
       return PIC_ERR_ARG;
@@ -815,11 +999,12 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
   unsigned long long stp = st->step;
   if ((rc = h2d(sim, sim->pl.sim.step, &stp, 1)) != PIC_OK) return rc;
   const int p = static_cast<int>(stp & 1);
-  const int up = st->sort_all ? p ^ 1 : p;
+  const int up = sort_all ? p ^ 1 : p;
   for (int s = 0; s < 2; ++s) {
     const SpeciesDev& S = sim->pl.sp[2 * d + s];
     const uint32_t n = static_cast<uint32_t>(st->n[s]);
-    const uint32_t ns = st->sort_all ? n : static_cast<uint32_t>(st->n_sorted[s]);
+    const uint32_t ns = (sort_all || S.mode == kModeNone)
+                            ? n : static_cast<uint32_t>(st->n_sorted[s]);
     void* const* f = S.fld[up];
     if (fp32) {
       if ((rc = h2d(sim, static_cast<int32_t*>(f[F32_CELL]), st->cell[s], n))) return rc;
@@ -839,16 +1024,18 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
     if ((rc = h2d(sim, S.n_sorted + up, &cnt[1], 1))) return rc;
     const uint32_t nid = st->next_id[s];
     if ((rc = h2d(sim, S.next_id, &nid, 1))) return rc;
-    HIPCHECK(sim, hipMemsetAsync(S.far_w, 0, sizeof(double) * S.n_nodes, sim->stream));
+    launch_zero(S.far_w, sizeof(unsigned long long) * S.n_nodes, sim->stream);
   }
-  if (st->sort_all) {
+  if (sort_all) {
     // the general sort covers every species; keep the other discharges' buffers intact by
     // sorting only when this is the only discharge
     if (sim->pl.li.n_ds != 1) {
-      sim->err = "pic_set_state: sort_all is only available for a single discharge";
+      sim->err = "pic_set_state: sort_all (and a fine-sorted state) is only available for a "
+                 "single discharge";
       return PIC_ERR_ARG;
     }
     launch_general_sort(sim->pl.li, sim->pl.d_sim, up, p, sim->stream);
+    if (fine) launch_fine_scatter(sim->pl.li, sim->pl.d_sim, p, sim->stream);
   } else {
     for (int s = 0; s < 2; ++s) launch_cell_start(sim->pl.li, sim->pl.d_sim, 2 * d + s, p, sim->stream);
   }

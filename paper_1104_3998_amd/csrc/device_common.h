@@ -208,6 +208,58 @@ __device__ __forceinline__ int push64(double x, double vx, double e0, double e1,
 }
 
 // ------------------------------------------------------------------------------------
+// Electrode processes (Sec. 2: electrons inserted at the boundaries when secondary
+// emission or reflection is featured).  A reflected electron is mirrored in the wall it
+// crossed (x -> -x or 2N - x, v_x -> -v_x); st is its wall status (1: x < 0, 2: x >= N).
+// Returns whether the mirrored position is inside the box.
+// ------------------------------------------------------------------------------------
+// FP32 cell + offset: cell c, offset f -> cell -c - 1 (or 2N - c - 1), offset 1 - f.
+__device__ __forceinline__ bool mirror32(int N, int st, int& d, float& f) {
+  int cn = st == 1 ? -d - 1 : 2 * N - d - 1;
+  float fn = 1.0f - f;
+  if (fn >= 1.0f) {
+    fn = 0.0f;
+    cn += 1;
+  }
+  d = cn;
+  f = fn;
+  return cn >= 0 && cn < N;
+}
+
+__device__ __forceinline__ bool mirror64(int N, int st, double& x, int& d) {
+  const double dn = static_cast<double>(N);
+  x = st == 1 ? -x : 2.0 * dn - x;
+  if (!(x >= 0.0 && x < dn)) return false;
+  d = static_cast<int>(floor(x));
+  return true;
+}
+
+// Secondary electron of an ion absorbed at wall st (1: x = 0, 2: x = N), from the ion's
+// Philox blocks 7 and 8 (block 6 word 0 decided the emission): normal speed Rayleigh-
+// distributed with scale vth (the flux of a Maxwellian through the wall), tangential
+// components normal, starting a uniform fraction of its first step's flight from the wall.
+// Returns whether the start position is inside the box.
+__device__ __forceinline__ bool emitted_electron(int N, int st, double vth, uint4 b7, uint4 b8,
+                                                 double& x, double v[3]) {
+  const double ua = u53(b7.x, b7.y);
+  const double uf = u53(b7.z, b7.w);
+  const double vn = vth * sqrt(-2.0 * log(1.0 - ua));
+  double z0, z1;
+  normals64(b8, z0, z1);
+  const double dn = static_cast<double>(N);
+  if (st == 1) {
+    v[0] = vn;
+    x = uf * vn;
+  } else {
+    v[0] = -vn;
+    x = dn - uf * vn;
+  }
+  v[1] = vth * z0;
+  v[2] = vth * z1;
+  return x >= 0.0 && x < dn;
+}
+
+// ------------------------------------------------------------------------------------
 // Tile-window geometry.  Cell tile t of a species owns cells [tC, tC + C); its window
 // starts at cell tC - D.  A histogram window spans W = C + 2D cells, a deposit window
 // W + 1 nodes.  for_covering visits, in increasing tile index, every tile whose window
@@ -362,6 +414,18 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 // ------------------------------------------------------------------------------------
+// Fixed-point charge weights.  A particle at in-cell offset f adds 1 - f to the node on
+// its left and f to the node on its right (Sec. 3.4).  The library adds them as the
+// integers one - F and F with F = round(f 2^shift): integer sums are exact whatever the
+// order of the additions, so the node weights come out bit for bit the same however the
+// work is scheduled.  shift leaves room for the species' whole capacity in 64 bits.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long fix_weight(double f, double scale) {
+  // f * scale < 2^53: the product is exact and rint gives the nearest integer
+  return static_cast<unsigned long long>(rint(f * scale));
+}
+
+// ------------------------------------------------------------------------------------
 // Workgroup scans (fixed summation order, so results do not depend on scheduling).
 // ------------------------------------------------------------------------------------
 template <class T>
@@ -399,12 +463,25 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T& total) {
   return ex;
 }
 
-// In-place exclusive scan of a[0..n) by one workgroup; returns the total.  The barriers
-// make the workgroup's own global stores visible to it (its waves share one CU); no
-// device-scope fence, which on this GPU writes back the whole L2.
+// Sum of one value per thread over the workgroup in a fixed order (a butterfly inside
+// each wave, then the waves in order); `lds` holds blockDim/64 entries.  Every thread
+// gets the total.
+template <class T>
+__device__ __forceinline__ T block_sum_fixed(T v, T* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  T r = T(0);
+  for (int i = 0; i < nw; ++i) r = r + lds[i];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan of src[0..n) into dst[0..n) by one workgroup (no copy of src to dst
+// first); returns the total.  The caller orders any earlier writes of src with a barrier.
 template <class T, class Ptr>
 __device__ T array_exclusive_scan_to(Ptr src, Ptr dst, int n, T* lds) {
-  // the same scan, reading src and writing dst (no copy of src to dst first)
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per;
   const int hi = lo + per < n ? lo + per : n;
@@ -421,6 +498,9 @@ __device__ T array_exclusive_scan_to(Ptr src, Ptr dst, int n, T* lds) {
   return total;
 }
 
+// In-place exclusive scan of a[0..n) by one workgroup; returns the total.  The barriers
+// make the workgroup's own global stores visible to it (its waves share one CU); no
+// device-scope fence, which on this GPU writes back the whole L2.
 template <class T, class Ptr>
 __device__ T array_exclusive_scan(Ptr a, int n, T* lds) {
   __syncthreads();

@@ -2,6 +2,7 @@
 // load, the general stable counting sort by cell (used once at load time and for states
 // handed in unsorted), the charge deposit of a sorted state and the half-step back-push
 // that starts the leap-frog (Sec. 3.6).
+#include <algorithm>
 #include <type_traits>
 
 #include "device_common.h"
@@ -233,7 +234,6 @@ __global__ __launch_bounds__(256) void k_cell_start(const SimDev* __restrict__ s
 template <class P>
 __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict__ simp,
                                                        int ds_filter) {
-  using real = typename Rec<P>::real;
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
   const SpeciesDev s = sim.sp[tt.x];
@@ -241,10 +241,20 @@ __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict_
   const int p = static_cast<int>(*sim.step & 1ull);
   const int t = tt.y;
   const int N = s.n_cells, W = s.W;
-  __shared__ real dep[kMaxWindow + 1];
+  // fixed-point node weights of the window (integer atomics: exact in any order)
+  __shared__ unsigned long long dep[kMaxWindow + 1];
   uint32_t lo, hi;
-  const bool tail = t >= s.n_tiles;
-  if (!tail) {
+  const bool tail = (t >= s.n_tiles || s.mode == kModeNone) && s.mode != kModeFine;
+  void GM* const* f = s.mode == kModeFine ? s.fine : s.fld[p];
+  if (s.mode == kModeFine) {
+    lo = static_cast<uint32_t>(t) * s.nmax;
+    hi = lo + min(s.fcnt[t], s.nmax);
+  } else if (s.mode == kModeNone) {
+    const uint32_t nt = s.n_total[p];
+    const uint32_t per = (nt + s.n_tiles - 1) / s.n_tiles;
+    lo = min(nt, static_cast<uint32_t>(t) * per);
+    hi = min(nt, lo + per);
+  } else if (!tail) {
     const uint32_t* cs = s.cell_start + p * (N + 1);
     lo = cs[t * s.C];
     hi = cs[min(t * s.C + s.C, N)];
@@ -255,39 +265,36 @@ __global__ __launch_bounds__(256) void k_deposit_tiles(const SimDev* __restrict_
     lo = min(nt, ns + static_cast<uint32_t>(t - s.n_tiles) * per);
     hi = min(nt, lo + per);
   }
-  for (int k = threadIdx.x; k <= W; k += blockDim.x) dep[k] = real(0);
+  for (int k = threadIdx.x; k <= W; k += blockDim.x) dep[k] = 0ull;
   __syncthreads();
-  void GM* const* f = s.fld[p];
   for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     int c;
     double fr;
-    real frr;
     if constexpr (std::is_same<P, S32>::value) {
       c = static_cast<const int GM*>(f[F32_CELL])[i];
-      frr = static_cast<const float GM*>(f[F32_OFF])[i];
-      fr = static_cast<double>(frr);
+      fr = static_cast<double>(static_cast<const float GM*>(f[F32_OFF])[i]);
     } else {
       const double x = static_cast<const double GM*>(f[F64_X])[i];
       const double cc = floor(x);
       c = static_cast<int>(cc);
       fr = x - cc;
-      frr = fr;
     }
     if (c < 0 || c >= N) continue;
+    const unsigned long long F = fix_weight(fr, s.dep_scale);
     const int k = tail ? -1 : window_slot(s, t, c);
     if (k >= 0) {
-      atomicAdd(&dep[k], real(1) - frr);
-      atomicAdd(&dep[k + 1], frr);
+      atomicAdd(&dep[k], s.dep_one - F);
+      atomicAdd(&dep[k + 1], F);
     } else {
       int cn = c + 1;
       if (s.periodic && cn == N) cn = 0;
-      atomicAdd(&s.far_w[c], 1.0 - fr);
-      atomicAdd(&s.far_w[cn], fr);
+      atomicAdd(&s.far_w[c], s.dep_one - F);
+      atomicAdd(&s.far_w[cn], F);
     }
   }
   __syncthreads();
   if (!tail) {
-    real* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(t) * (W + 1);
+    unsigned long long GM* part = s.partial + static_cast<size_t>(t) * (W + 1);
     for (int k = threadIdx.x; k <= W; k += blockDim.x) part[k] = dep[k];
   }
 }
@@ -300,8 +307,13 @@ __global__ __launch_bounds__(256) void k_halfstep(const SimDev* __restrict__ sim
   const DischargeDev dd = sim.ds[s.ds];
   const int p = static_cast<int>(*sim.step & 1ull);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s.n_total[p]) return;
   void GM* const* f = s.fld[p];
+  if (s.mode == kModeFine) {  // slot i of sorting cell i / nmax
+    if (i >= s.cap || (i % s.nmax) >= s.fcnt[i / s.nmax]) return;
+    f = s.fine;
+  } else if (i >= s.n_total[p]) {
+    return;
+  }
   const int N = s.n_cells;
   if constexpr (std::is_same<P, S32>::value) {
     const int c = static_cast<const int GM*>(f[F32_CELL])[i];
@@ -329,9 +341,24 @@ __global__ __launch_bounds__(256) void k_halfstep(const SimDev* __restrict__ sim
   }
 }
 
+// Zero fill of n 8-byte words (a kernel rather than a memset node, so that the same code
+// stays correct if a caller records it into a HIP graph).
+__global__ __launch_bounds__(256) void k_zero(unsigned long long* p, size_t n) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x)
+    p[i] = 0ull;
+}
+
 // ------------------------------------------------------------------------------------
 // host launchers
 // ------------------------------------------------------------------------------------
+void launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 8;
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+  k_zero<<<static_cast<unsigned>(blocks), 256, 0, st>>>(static_cast<unsigned long long*>(p), n);
+}
+
 void launch_load(const LaunchInfo& li, const SimDev* sim, int dst_buf, hipStream_t st) {
   dim3 grid((li.max_cap + 255) / 256, li.n_spec);
   if (li.fp32) k_load<S32><<<grid, 256, 0, st>>>(sim, dst_buf);

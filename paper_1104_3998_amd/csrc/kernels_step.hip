@@ -13,8 +13,10 @@
 // A tile is the set of particles of C consecutive cells (the paper puts one sorting cell
 // per thread block, Sec. 3.2); the output of a tile's particles can only land within D
 // cells of its cells except for rare far movers, so the stable counting sort needs
-// only a (C + 2D)-slot histogram per tile.  No global float atomics are used on the
-// bulk path; far movers and births (a small fraction) add into a per-node FP64 array.
+// only a (C + 2D)-slot histogram per tile.  Charge is deposited as fixed-point integers
+// (device_common.h, fix_weight): the bulk into per-tile LDS windows, far movers, tail
+// particles and births (a small fraction) into a per-node array with integer atomics, so
+// every node weight is an exact, order-independent sum.
 #include <hip/hip_ext.h>
 
 #include <type_traits>
@@ -36,9 +38,16 @@ struct RecPtr {
   uint32_t boff4, boff8;
 };
 
-// buffer b of the species' particle arrays
+// buffer b of the species' particle arrays (a fine-sorted species has one set of arrays,
+// sorted in place)
 __device__ __forceinline__ RecPtr rec_buf(const SpeciesDev CM* s, int b) {
   RecPtr r;
+  if (s->mode == kModeFine) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r.f[k] = s->fine[k];
+    r.boff4 = r.boff8 = 0u;
+    return r;
+  }
 #pragma unroll
   for (int k = 0; k < 6; ++k) r.f[k] = s->fld[0][k];
   r.boff4 = b ? s->bstride4 : 0u;
@@ -197,14 +206,54 @@ __device__ __forceinline__ void store_record(const RecPtr& f, uint32_t i, int d,
   if constexpr (kWithId) sto<uint32_t>(f.f[F_ID], o4, id);
 }
 
+// In-place update of a fine-sorted particle's position and v_x (the other fields do not
+// change in the push); a particle that left the box gets the dead marker (cell -1, or a
+// negative x) that k_fine_sort1 removes.
+template <class P>
+__device__ __forceinline__ void store_in_place(const RecPtr& f, uint32_t i, bool alive, int d,
+                                               typename Part<P>::real pos,
+                                               typename Part<P>::real vx) {
+  const uint32_t o4 = f.boff4 + i * 4u;
+  if constexpr (std::is_same<P, P32>::value) {
+    sto<int>(f.f[F32_CELL], o4, alive ? d : -1);
+    sto<float>(f.f[F32_OFF], o4, pos);
+    sto<float>(f.f[F_VX], o4, vx);
+  } else {
+    const uint32_t o8 = f.boff8 + i * 8u;
+    sto<double>(f.f[F64_X], o8, alive ? pos : -1.0);
+    sto<double>(f.f[F_VX], o8, vx);
+  }
+}
+
 struct TileRange {
   uint32_t lo, hi;
   int c0;
   bool tail;
+  bool fine;  // a sorting cell of a fine-sorted species
 };
 
 __device__ __forceinline__ TileRange tile_range(const SpeciesDev& s, int t, int p) {
   TileRange r;
+  r.fine = false;
+  if (s.mode == kModeFine) {
+    // sorting cell t: its slots in the fine arrays
+    r.tail = false;
+    r.fine = true;
+    r.c0 = t * s.C;
+    r.lo = static_cast<uint32_t>(t) * s.nmax;
+    r.hi = r.lo + min(s.fcnt[t], s.nmax);
+    return r;
+  }
+  if (s.mode == kModeNone) {
+    // unsorted: the array [0, n) cut into n_tiles equal ranges, handled like tail tiles
+    r.tail = true;
+    r.c0 = 0;
+    const uint32_t nt = s.n_total[p];
+    const uint32_t per = (nt + s.n_tiles - 1) / s.n_tiles;
+    r.lo = min(nt, static_cast<uint32_t>(t) * per);
+    r.hi = min(nt, r.lo + per);
+    return r;
+  }
   r.tail = t >= s.n_tiles;
   if (!r.tail) {
     r.c0 = t * s.C;
@@ -315,7 +364,7 @@ __device__ __forceinline__ void stream_range_rev(uint32_t lo, uint32_t hi, Load&
 // at the end of both passes) instead of once early and once late, when a half-written
 // line has long been written back.
 __device__ __forceinline__ bool wave_reversed(const TileRange& r, int w) {
-  return !r.tail && (w & 1) == 0;
+  return !r.tail && !r.fine && (w & 1) == 0;
 }
 
 // The fields the push reads (the sort pre-pass loads only these).
@@ -413,6 +462,20 @@ __device__ __forceinline__ int push_particle(const SpeciesDev& s, const Discharg
   }
 }
 
+// Electrode reflection of an electron that reached a wall (st 1 or 2; Sec. 2), decided by
+// word 0 of its Philox block 6: returns the new status, 0 when mirrored back into the box.
+template <class P>
+__device__ __forceinline__ int reflect_at_wall(const SpeciesDev& s, uint32_t id, uint32_t step32,
+                                               int st, int& d, typename Part<P>::real& pos,
+                                               typename Part<P>::real& vxn) {
+  if (!(philox(id, step32, 6u, 0u, s.key0, s.key1).x < s.t_refl)) return st;
+  bool in;
+  if constexpr (std::is_same<P, P32>::value) in = mirror32(s.n_cells, st, d, pos);
+  else in = mirror64(s.n_cells, st, pos, d);
+  vxn = -vxn;
+  return in ? 0 : st;
+}
+
 __device__ __forceinline__ bool diag_step(const DischargeDev& dd, unsigned long long step) {
   if (dd.eedf_bins <= 0 || dd.diag_every <= 0) return false;
   const long long st = static_cast<long long>(step);
@@ -427,7 +490,6 @@ __device__ __forceinline__ bool diag_step(const DischargeDev& dd, unsigned long 
 // meet in a fixed butterfly, so the result is reproducible.  Grid: one workgroup per
 // block of kCombineNodes nodes of a species (node_table).
 // ====================================================================================
-template <class real>
 __global__ __launch_bounds__(kCombineNodes * kCombineLanes) void k_combine(
     const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
@@ -436,22 +498,24 @@ __global__ __launch_bounds__(kCombineNodes * kCombineLanes) void k_combine(
   const int l = static_cast<int>(threadIdx.x) % kCombineLanes;
   const int j = nt.y + static_cast<int>(threadIdx.x) / kCombineLanes;
   const bool live = j < s.n_nodes;  // the butterfly below needs every lane of a node
-  const real GM* part = static_cast<const real GM*>(s.partial);
+  const unsigned long long GM* part = s.partial;
   const int span = s.W + 1;
-  double sum = 0.0;
-  if (live) {
+  unsigned long long sum = 0ull;
+  if (live && s.mode != kModeNone) {  // unsorted: every deposit is in the node array
     int a[2], b[2];
     covering_ranges(s, j, span, a, b);
     const int n0 = b[0] >= a[0] ? b[0] - a[0] + 1 : 0;
     const int n1 = b[1] >= a[1] ? b[1] - a[1] + 1 : 0;
     for (int u = l; u < n0 + n1; u += kCombineLanes) {
       const int t = u < n0 ? a[0] + u : a[1] + (u - n0);
-      sum += static_cast<double>(part[static_cast<size_t>(t) * span + covering_slot(s, j, t)]);
+      sum += part[static_cast<size_t>(t) * span + covering_slot(s, j, t)];
     }
   }
 #pragma unroll
-  for (int o = kCombineLanes / 2; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
-  if (live && l == 0) sim.ds[s.ds].w[s.sp][j] = sum + s.far_w[j];
+  for (int o = kCombineLanes / 2; o >= 1; o >>= 1)
+    sum += static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(sum), o, 64));
+  if (live && l == 0)
+    sim.ds[s.ds].w[s.sp][j] = static_cast<double>(sum + s.far_w[j]) * s.dep_inv;
 }
 
 // ====================================================================================
@@ -462,6 +526,13 @@ __global__ __launch_bounds__(kCombineNodes * kCombineLanes) void k_combine(
 // s_j = s_0 - R_j with R_j = sum_{k=1..j} rho_k, s_0 fixed by the two end potentials;
 // Phi is the running sum of s.  E_j = -(s_{j-1} + s_j)/2 inside; at an electrode Gauss's
 // law over the half cell: E_0 = -s_0 - rho_0, E_N = -s_{N-1} + rho_N.
+// With a series capacitor C between the source V_s and the driven electrode (an external
+// circuit; Sec. 3.5 leaves boundary conditions to the literature), the electrode and the
+// plate joined to it hold the charge q, which changes only by the particles absorbed or
+// emitted there.  E_0 grows with Phi_0 as E_0 = sigma_z + Phi_0 / N (sigma_z: the value
+// for Phi_0 = 0), the plate holds q - E_0, and Phi_0 = V_s + (q - E_0) / C gives
+// Phi_0 = (V_s + (q - sigma_z) / C) / (1 + 1 / (N C)).
+// The step's net charge, field energy and electrode potential are kept for diagnostics.
 // ====================================================================================
 __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ simp,
                                                     int init_mode) {
@@ -484,6 +555,12 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
   const double rho_wallN = dd.periodic ? 0.0 : wi[N] - we[N];
   const int hc = min(hi, N);  // the thread's cells
   double total;
+  double sum_rho;
+  {
+    double part = 0.0;
+    for (int j = lo; j < hi; ++j) part += sv[j];
+    sum_rho = block_sum_fixed(part, lds_d);
+  }
   // mean charge (periodic only)
   double mean = 0.0;
   if (dd.periodic) {
@@ -508,7 +585,22 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
     for (int j = lo; j < hc; ++j) part += sv[j];
     block_exclusive_scan(part, lds_d, sum_r);
   }
-  const double a = dd.periodic ? 0.0 : dd.vhat_amp * sin(dd.phase_per_step * static_cast<double>(step));
+  const double vs = dd.periodic ? 0.0 : dd.vhat_amp * sin(dd.phase_per_step * static_cast<double>(step));
+  double a = vs;
+  double q = 0.0;
+  if (dd.cap_norm > 0.0) {
+    const double sigma_z = -(sum_r / static_cast<double>(N)) - rho_wall0;
+    if (init_mode) {
+      q = sigma_z + vs / static_cast<double>(N);  // capacitor uncharged at the load
+    } else {
+      const SpeciesDev se = sim.sp[dd.spec0];
+      const SpeciesDev si = sim.sp[dd.spec0 + 1];
+      q = dd.dstat[DS_Q_INIT] + static_cast<double>(si.absorbed[0]) -
+          static_cast<double>(se.absorbed[0]) + static_cast<double>(si.emitted[0]);
+    }
+    a = (vs + (q - sigma_z) / dd.cap_norm) /
+        (1.0 + 1.0 / (static_cast<double>(N) * dd.cap_norm));
+  }
   const double s0 = (0.0 - a + sum_r) / static_cast<double>(N);
   // s_j = s0 - R_j and Phi_j = a + sum_{m<j} s_m
   double GM* phi = dd.phi;
@@ -524,7 +616,12 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
     }
   }
   if (!dd.periodic && tid == 0) phi[N] = 0.0;
-  __syncthreads();
+  double field;
+  {
+    double part = 0.0;
+    for (int j = lo; j < hc; ++j) part += sv[j] * sv[j];
+    field = 0.5 * block_sum_fixed(part, lds_d);  // also orders the slope stores above
+  }
   // E from the slopes
   for (int j = lo; j < hi; ++j) {
     double e;
@@ -541,6 +638,13 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
     dd.E64[j] = e;
     dd.E32[j] = static_cast<float>(e);
   }
+  if (tid == 0) {
+    dd.dstat[DS_FIELD] = field;
+    dd.dstat[DS_SUM_RHO] = sum_rho;
+    dd.dstat[DS_PHI0] = dd.periodic ? 0.0 : a;
+    dd.dstat[DS_Q] = q;
+    if (init_mode) dd.dstat[DS_Q_INIT] = q;
+  }
   if (!init_mode && static_cast<long long>(step) >= dd.avg_start) {
     for (int j = tid; j < nn; j += blockDim.x) {
       dd.acc_w[0][j] += we[j];
@@ -550,12 +654,15 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
     if (tid == 0) *dd.acc_count += 1ull;
   }
   if (!init_mode && tid == 0 && diag_step(dd, step)) *dd.eedf_samples += 1ull;
-  // per-step far-mover state of both species starts empty
-  for (int sp = 0; sp < 2; ++sp) {
+  // per-step far-mover state of both species starts empty; a fine-sorted species counts
+  // its survivors into n_sorted of the step's output parity.  (Not at the load: the far
+  // array then holds part of the load's deposit, which the first step's combine reads.)
+  for (int sp = 0; sp < 2 && !init_mode; ++sp) {
     const SpeciesDev s = sim.sp[dd.spec0 + sp];
-    for (int j = tid; j < nn; j += blockDim.x) s.far_w[j] = 0.0;
+    for (int j = tid; j < nn; j += blockDim.x) s.far_w[j] = 0ull;
     for (int c = tid; c < N; c += blockDim.x) s.far_cell_cnt[c] = 0u;
     if (tid == 0) *s.far_count = 0u;
+    if (tid == 0 && s.mode == kModeFine) s.n_sorted[(step + 1ull) & 1ull] = 0u;
   }
 }
 
@@ -586,8 +693,11 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
   const SpeciesDev s = sim.sp[tt.x];
+  if (s.mode == kModeFine) return;  // sorted in place after the push: no pre-pass
   const DischargeDev dd = sim.ds[s.ds];
-  const int p = static_cast<int>(*sim.step & 1ull);
+  const unsigned long long step = *sim.step;
+  const uint32_t step32 = static_cast<uint32_t>(step);
+  const int p = static_cast<int>(step & 1ull);
   const TileRange r = tile_range(s, tt.y, p);
   __shared__ real Elds[kMaxCellsPerTile + 1];
   __shared__ uint32_t hq[kWaves][64][2];
@@ -632,6 +742,9 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
           int st = 4, d = 0;
           real pos, vxn;
           if (valid) st = push_particle<P, false>(s, dd, Elds, r, q, d, pos, vxn);
+          if (s.t_refl && (st == 1 || st == 2))
+            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], in.boff4 + i * 4u), step32, st,
+                                    d, pos, vxn);
           const int k = st == 0 ? window_slot(s, tt.y, d) : -1;
           const bool near = k >= 0;
           if (near) atomicAdd(&hl[k], 1u);
@@ -655,6 +768,20 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
       for (int c = 0; c < kHistCopies; ++c) n += h[c * Wm + k];
       row[k] = n;
     }
+  } else if (s.mode == kModeNone) {
+    // unsorted: survivors of the wave's piece, in input order
+    uint32_t cnt = 0u;  // wave-uniform
+    stream_range<PushIn<P>, HistU<P>::value>(
+        wr.lo, wr.hi, load, [&](const PushIn<P>& q, uint32_t i, bool valid) {
+          int st = 4, d = 0;
+          real pos, vxn;
+          if (valid) st = push_particle<P, true>(s, dd, Elds, r, q, d, pos, vxn);
+          if (s.t_refl && (st == 1 || st == 2))
+            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], in.boff4 + i * 4u), step32, st,
+                                    d, pos, vxn);
+          cnt += static_cast<uint32_t>(__popcll(__ballot(st == 0)));
+        });
+    if (lane == 0) s.hist[tt.y * kWaves + wv] = cnt;
   } else {
     uint32_t GM* row = s.thist +
                     static_cast<size_t>((tt.y - s.n_tiles) * kWaves + wv) * s.n_cells;
@@ -663,6 +790,9 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
           int st = 4, d = 0;
           real pos, vxn;
           if (valid) st = push_particle<P, true>(s, dd, Elds, r, q, d, pos, vxn);
+          if (s.t_refl && (st == 1 || st == 2))
+            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], in.boff4 + i * 4u), step32, st,
+                                    d, pos, vxn);
           if (st == 0) atomicAdd(&row[d], 1u);
         });
   }
@@ -774,6 +904,13 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
   const int q = static_cast<int>((*sim.step + 1ull) & 1ull);
   const int N = s.n_cells, W = s.W;
+  if (s.mode == kModeFine) return;
+  if (s.mode == kModeNone) {
+    // unsorted: each (tile, wave) unit's survivors start after those of the units before
+    const uint32_t n_surv = array_exclusive_scan_to(s.hist, s.tilerel, s.n_tiles * kWaves, lds);
+    if (threadIdx.x == 0) s.n_sorted[q] = n_surv;
+    return;
+  }
   const uint32_t fc = *s.far_count;
   const uint32_t F = fc < s.far_cap ? fc : s.far_cap;
   if (threadIdx.x == 0 && fc > s.far_cap) atomicOr(sim.error, kErrFarOverflow);
@@ -847,23 +984,24 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
 constexpr uint32_t kNoDest = 0xFFFFFFFFu;
 constexpr int kFarQ = 64;           // per-wave queue of far movers (one chunk always fits)
 
-template <class real>
-struct DepCopies {
-  static constexpr int value = sizeof(real) == 4 ? 8 : 4;
-};
+// Copies of the tile's deposit window: lane l adds into copy l mod kDepCopies, so one
+// atomic instruction has few lanes on any one address (the 64 particles of a chunk come
+// from one cell and land in a handful of slots).
+constexpr int kDepCopies = 8;
 
 template <class P>
 struct MainShared {
   using real = typename Part<P>::real;
   real Elds[kMaxCellsPerTile + 1];
   uint32_t off[kWaves][kMaxWindow];  // next output index of each (wave, window slot)
-  // deposit window in kDepCopies copies shared by the waves; lane l adds into copy
-  // l mod kDepCopies, so one atomic instruction has few lanes on any one address (the
-  // 64 particles of a chunk come from one cell and land in a handful of slots)
-  real dep[DepCopies<real>::value][kMaxWindow + 1];
+  // sum of the fixed-point right-node weights F of the near particles of each window slot,
+  // in kDepCopies copies shared by the waves; the slot's particle count comes from the
+  // tile's histogram rows, so the left node's share (count * one - sum F) needs no atomics
+  unsigned long long dep[kDepCopies][kMaxWindow];
+  uint32_t cnt[kMaxWindow];          // fine sort: near particles per window slot
   uint32_t eedf[kMaxEedfBins + 1];
-  uint32_t abs_cnt[2];
-  double abs_e[2];
+  double wst[kWaves][4];             // per-wave sums: kinetic, momentum, absorbed energy x2
+  uint32_t wcnt[kWaves][6];          // per-wave counts: absorbed, emitted, reflected x2
   uint32_t err;                      // error bits found by the tile
   // far movers deferred to the end of each wave's loop: index, cell, position word,
   // vx, vy, vz (FP32 bits), id, candidate entry; FP64 keeps the reals in fqd
@@ -981,34 +1119,29 @@ __device__ int collide(const SpeciesDev& s, uint32_t id, uint32_t step, uint32_t
   return ch;
 }
 
+// Fixed-point weight F = round(f 2^shift) of the right-hand node of a particle's cell
+// (Sec. 3.4: the left-hand node takes one - F); pos is the FP32 offset or the FP64 x.
 template <class P>
-__device__ __forceinline__ void far_deposit(const SpeciesDev& s, int d,
-                                            typename Part<P>::real pos) {
+__device__ __forceinline__ unsigned long long right_weight(const SpeciesDev& s,
+                                                           typename Part<P>::real pos) {
   double f;
   if constexpr (std::is_same<P, P32>::value) {
     f = static_cast<double>(pos);
   } else {
     f = pos - floor(pos);
   }
-  int dn = d + 1;
-  if (s.periodic && dn == s.n_cells) dn = 0;
-  atomicAdd(&s.far_w[d], 1.0 - f);
-  atomicAdd(&s.far_w[dn], f);
+  return fix_weight(f, s.dep_scale);
 }
 
-// Weights of a particle's deposit onto the two nodes of its cell (Sec. 3.4).
+// Deposit of one particle in cell d straight into the per-node array (integer atomics).
 template <class P>
-__device__ __forceinline__ void deposit_weights(typename Part<P>::real pos,
-                                                typename Part<P>::real& w0,
-                                                typename Part<P>::real& w1) {
-  if constexpr (std::is_same<P, P32>::value) {
-    w0 = 1.0f - pos;
-    w1 = pos;
-  } else {
-    const double f = pos - floor(pos);
-    w0 = 1.0 - f;
-    w1 = f;
-  }
+__device__ __forceinline__ void far_deposit(const SpeciesDev& s, int d,
+                                            typename Part<P>::real pos) {
+  const unsigned long long F = right_weight<P>(s, pos);
+  int dn = d + 1;
+  if (s.periodic && dn == s.n_cells) dn = 0;
+  atomicAdd(&s.far_w[d], s.dep_one - F);
+  atomicAdd(&s.far_w[dn], F);
 }
 
 // Chunks of 64 particles per pass of a wave's loop.  Besides keeping loads in flight, a
@@ -1026,8 +1159,10 @@ struct MainU<P64> {
   static constexpr int value = 3;
 };
 
+// Four waves per SIMD (at most 128 VGPRs): with fewer, too few loads are in flight.
 template <class P>
-__global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_main(
+    const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int2 tt = sim.tile_table[blockIdx.x];
@@ -1041,15 +1176,17 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   __shared__ MainShared<P> sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const unsigned long long lt = lanes_below(), gt = lanes_above();
-  const bool eedf_on = s.sp == 0 && diag_step(dd, step);
-  const bool far_ok = (*sim.error & kErrFarOverflow) == 0u;
+  const bool energy_on = diag_step(dd, step);
+  const bool eedf_on = s.sp == 0 && energy_on;
+  // after a far-list overflow or an overfull far group, far_dest is not valid this step
+  const bool far_ok = (*sim.error & (kErrFarOverflow | kErrFarGroup)) == 0u;
   const uint32_t n_out = s.n_sorted[pq];
   const uint32_t sink = s.cap;  // the extra element past the capacity of every array
   const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
                                                   : reinterpret_cast<const real GM*>(dd.E64);
   load_field_window<real>(s, E, r, sh.Elds);
   const int W = s.W;
-  if (!r.tail) {
+  if (!r.tail && !r.fine) {
     for (int k = tid; k < kWaves * W; k += kWG) {
       const int w = k / W, kk = k - w * W;
       int c = tile * s.C - s.D + kk;
@@ -1065,16 +1202,20 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
                           : 0u;
     }
   }
-  constexpr int kCopies = DepCopies<real>::value;
-  for (int k = tid; k < kCopies * (W + 1); k += kWG) sh.dep[k / (W + 1)][k % (W + 1)] = real(0);
+  for (int k = tid; k < kDepCopies * W; k += kWG) sh.dep[k / W][k % W] = 0ull;
+  if (r.fine)
+    for (int k = tid; k < W; k += kWG) sh.cnt[k] = 0u;
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG) sh.eedf[k] = 0u;
-  if (tid == 0) {
-    sh.abs_cnt[0] = sh.abs_cnt[1] = 0u;
-    sh.abs_e[0] = sh.abs_e[1] = 0.0;
-    sh.err = 0u;
-  }
+  if (tid == 0) sh.err = 0u;
+  if (tid < kWaves * 4) sh.wst[tid / 4][tid % 4] = 0.0;
   __syncthreads();
+  // Sums of the tile are built chunk by chunk in a fixed order (a butterfly over the
+  // chunk's lanes, added to the wave's own LDS entry), so no per-lane accumulator stays
+  // live through the particle loop.
+  uint32_t n_abs0 = 0u, n_abs1 = 0u;    // wave-uniform
+  uint32_t n_wall[4] = {0u, 0u, 0u, 0u};  // emitted x2 (k_emit), reflected x2 (wave-uniform)
+  uint32_t n_em = 0u;                   // absorbed ions listed by this wave (emission)
   const WaveRange wr = wave_range(r, wv);
   const RecPtr in = rec_buf(&sim.sp[tt.x], p);
   const RecPtr out = rec_buf(&sim.sp[tt.x], pq);
@@ -1082,26 +1223,69 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
   auto load = [&](Part<P>& q, uint32_t i) { q.load(in, i); };
 
   // Push, walls, EEDF and the null-collision test: common to both kinds of tile.
-  auto push_and_test = [&](auto tail_tag, const Part<P>& q, bool valid, int& d, real& pos,
-                           real& vxn, bool& cand) {
+  // Push, walls (reflection, absorption, emission), EEDF, energy sums and the
+  // null-collision test: common to both kinds of tile.
+  auto push_and_test = [&](auto tail_tag, auto rev_tag, const Part<P>& q, bool valid, int& d,
+                           real& pos, real& vxn, bool& cand) {
     constexpr bool kTail = decltype(tail_tag)::value;
+    constexpr bool kRev = decltype(rev_tag)::value;
     int st = 4;
     if (valid) st = push_particle<P, kTail>(s, dd, sh.Elds, r, q, d, pos, vxn);
-    if (valid && (eedf_on || st == 1 || st == 2)) {
-      const double v2 = static_cast<double>(vxn) * static_cast<double>(vxn) +
-                        static_cast<double>(q.vy) * static_cast<double>(q.vy) +
-                        static_cast<double>(q.vz) * static_cast<double>(q.vz);
-      if (eedf_on && st != 3) {
+    if (energy_on) {  // wave-uniform: after the push, before the walls
+      double v1 = 0.0, ke = 0.0, v2 = 0.0;
+      if (st < 3) {
+        const double vyz = static_cast<double>(q.vy) * static_cast<double>(q.vy) +
+                           static_cast<double>(q.vz) * static_cast<double>(q.vz);
+        v1 = static_cast<double>(vxn);
+        v2 = v1 * v1 + vyz;
+        // kinetic energy as the mean of v_x^2 before and after the push
+        const double v0 = static_cast<double>(q.vx);
+        ke = 0.5 * (v0 * v0 + v1 * v1) + vyz;
+      }
+      const double sk = wave_sum(ke), sm = wave_sum(v1);
+      if (lane == 0) {
+        sh.wst[wv][0] += sk;
+        sh.wst[wv][1] += sm;
+      }
+      if (eedf_on && st < 3) {
         const double b = floor(s.energy_c * v2 * dd.eedf_inv_width);
         const int bin = b >= static_cast<double>(dd.eedf_bins) ? dd.eedf_bins : static_cast<int>(b);
         atomicAdd(&sh.eedf[bin], 1u);
       }
-      if (st == 1 || st == 2) {
-        atomicAdd(&sh.abs_cnt[st - 1], 1u);
-        atomicAdd(&sh.abs_e[st - 1], s.energy_c * v2);
+    }
+    if (s.t_refl && __ballot(st == 1 || st == 2)) {  // electrons reaching an electrode
+      const int st0 = st;
+      if (st == 1 || st == 2) st = reflect_at_wall<P>(s, q.id, step32, st, d, pos, vxn);
+      n_wall[2] += static_cast<uint32_t>(__popcll(__ballot(st0 == 1 && st == 0)));
+      n_wall[3] += static_cast<uint32_t>(__popcll(__ballot(st0 == 2 && st == 0)));
+    }
+    const unsigned long long m_abs0 = __ballot(st == 1), m_abs1 = __ballot(st == 2);
+    if (m_abs0 | m_abs1) {  // wave-uniform
+      const double v1 = static_cast<double>(vxn);
+      const double vyz = static_cast<double>(q.vy) * static_cast<double>(q.vy) +
+                         static_cast<double>(q.vz) * static_cast<double>(q.vz);
+      const double e = s.energy_c * (v1 * v1 + vyz);
+      const double e0 = wave_sum(st == 1 ? e : 0.0), e1 = wave_sum(st == 2 ? e : 0.0);
+      if (lane == 0) {
+        sh.wst[wv][2] += e0;
+        sh.wst[wv][3] += e1;
+      }
+      n_abs0 += static_cast<uint32_t>(__popcll(m_abs0));
+      n_abs1 += static_cast<uint32_t>(__popcll(m_abs1));
+      if (s.t_see) {
+        // absorbed ions are listed at their place in this wave's list (input order, like
+        // the MCC candidates); k_emit decides their secondary emission
+        const unsigned long long am = m_abs0 | m_abs1;
+        if (st == 1 || st == 2) {
+          uint32_t e;
+          if constexpr (kRev) e = wr.hi - 1u - n_em - static_cast<uint32_t>(__popcll(am & gt));
+          else e = wr.lo + n_em + static_cast<uint32_t>(__popcll(am & lt));
+          if (e < s.cap) s.ab_list[e] = make_uint2(q.id, static_cast<uint32_t>(st));
+        }
+        n_em += static_cast<uint32_t>(__popcll(am));
       }
     }
-    if (st == 3) atomicOr(&sh.err, kErrState);
+    if (st == 3) atomicOr(&sh.err, kErrNonfinite);
     cand = false;
     if (st == 0 && s.t0 != 0u) cand = philox(q.id, step32, 0u, 0u, s.key0, s.key1).x < s.t0;
     return st;
@@ -1132,7 +1316,33 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
     cand_store<P>(s.cand, e, dst, id, d, pos, vx, vy, vz);
   };
 
-  if (!r.tail) {
+  if (r.fine) {
+    // Fine sort (the paper's pusher, Sec. 3.6 with Sec. 3.7 steps 1a/1b after it): every
+    // particle stays in its slot; survivors get their new cell, offset and v_x, absorbed
+    // ones a dead marker; k_fine_sort1..3 then move the ones that left the sorting cell.
+    uint32_t alive = 0u;  // wave-uniform
+    stream_range<Part<P>, MainU<P>::value>(
+        wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
+          int d = 0;
+          real pos = real(0), vxn = real(0);
+          bool cand;
+          const int st = push_and_test(std::false_type{}, std::false_type{}, q, valid, d, pos,
+                                       vxn, cand);
+          store_in_place<P>(out, valid ? i : sink, st == 0, d, pos, vxn);
+          list_candidate(std::false_type{}, cand, false, i, q, d, pos, vxn);
+          if (st == 0) {
+            const int k = window_slot(s, tile, d);
+            if (k >= 0) {
+              atomicAdd(&sh.cnt[k], 1u);
+              atomicAdd(&sh.dep[lane & (kDepCopies - 1)][k], right_weight<P>(s, pos));
+            } else {
+              far_deposit<P>(s, d, pos);
+            }
+          }
+          alive += static_cast<uint32_t>(__popcll(__ballot(st == 0)));
+        });
+    if (lane == 0 && alive) atomicAdd(&s.n_sorted[pq], alive);
+  } else if (!r.tail) {
     // Far movers (beyond the window) wait in a per-wave LDS queue until the loop is
     // done: their output index is a global load, and a load inside the loop would make
     // the loop wait for the next chunk's loads too.
@@ -1173,7 +1383,7 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
       int d = 0;
       real pos = real(0), vxn = real(0);
       bool cand;
-      const int st = push_and_test(std::false_type{}, q, valid, d, pos, vxn, cand);
+      const int st = push_and_test(std::false_type{}, rev_tag, q, valid, d, pos, vxn, cand);
       const int k = st == 0 ? window_slot(s, tile, d) : -1;
       const bool near = k >= 0;
       // stable rank inside this wave's unit of the order (from the unit's end backwards
@@ -1220,15 +1430,9 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
         }
         qn += static_cast<uint32_t>(__popcll(fm));
       }
-      // deposit of the near particles into this wave's window (LDS float atomics: the
-      // LDS pipe absorbs the same-slot conflicts, the vector ALU stays free)
-      if (near) {
-        real w0, w1;
-        deposit_weights<P>(pos, w0, w1);
-        real* dep = sh.dep[lane & (kCopies - 1)];
-        atomicAdd(&dep[k], w0);
-        atomicAdd(&dep[k + 1], w1);
-      }
+      // deposit of the near particles: the right-node weight into the slot's sum (LDS
+      // integer atomics: exact in any order; the LDS pipe absorbs the same-slot conflicts)
+      if (near) atomicAdd(&sh.dep[lane & (kDepCopies - 1)][k], right_weight<P>(s, pos));
     };
     if (wave_reversed(r, wv)) {
       stream_range_rev<Part<P>, MainU<P>::value>(
@@ -1242,6 +1446,33 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
           });
     }
     if (qn) flush();
+  } else if (s.mode == kModeNone) {
+    // Unsorted (the variant of Sec. 3.2 without fine sorting): survivors keep their input
+    // order, compacted after the survivors of the units before; every deposit goes
+    // straight into the node array with integer atomics.
+    uint32_t run = 0u;  // survivors written by this wave so far (wave-uniform)
+    const uint32_t ubase = s.tilerel[tile * kWaves + wv];
+    stream_range<Part<P>, MainU<P>::value>(
+        wr.lo, wr.hi, load, [&](const Part<P>& q, uint32_t i, bool valid) {
+          int d = 0;
+          real pos = real(0), vxn = real(0);
+          bool cand;
+          const int st = push_and_test(std::true_type{}, std::false_type{}, q, valid, d, pos, vxn,
+                                       cand);
+          const unsigned long long m = __ballot(st == 0);
+          uint32_t dst = kNoDest;
+          if (st == 0) {
+            dst = ubase + run + static_cast<uint32_t>(__popcll(m & lt));
+            if (dst >= n_out) {
+              atomicOr(&sh.err, kErrState);
+              dst = kNoDest;
+            }
+          }
+          store_record<P>(out, dst == kNoDest ? sink : dst, d, pos, vxn, q.vy, q.vz, q.id);
+          list_candidate(std::false_type{}, cand, false, dst, q, d, pos, vxn);
+          if (dst != kNoDest) far_deposit<P>(s, d, pos);
+          run += static_cast<uint32_t>(__popcll(m));
+        });
   } else {
     // Tail tile: rank per cell against this wave's global tail row, one returning atomic
     // per (cell, chunk) by the group leader; deposits go to the far array.
@@ -1252,7 +1483,8 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
           int d = 0;
           real pos = real(0), vxn = real(0);
           bool cand;
-          const int st = push_and_test(std::true_type{}, q, valid, d, pos, vxn, cand);
+          const int st = push_and_test(std::true_type{}, std::false_type{}, q, valid, d, pos, vxn,
+                                       cand);
           const bool act = st == 0;
           const unsigned long long mc = match_key(d, act, nbits);
           const int rank = __popcll(mc & lt);
@@ -1273,24 +1505,60 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
           if (dst != kNoDest) far_deposit<P>(s, d, pos);
         });
   }
-  if (lane == 0) s.cand_cnt[tile * kWaves + wv] = n_cand;
+  if (lane == 0) {
+    s.cand_cnt[tile * kWaves + wv] = n_cand;
+    sh.wcnt[wv][0] = n_abs0;
+    sh.wcnt[wv][1] = n_abs1;
+    for (int k = 0; k < 4; ++k) sh.wcnt[wv][2 + k] = n_wall[k];
+    if (s.t_see) {
+      s.ab_cnt[tile * kWaves + wv] = n_em;
+      s.em_lo[tile * kWaves + wv] = wave_reversed(r, wv) ? wr.hi - n_em : wr.lo;
+    }
+  }
   __syncthreads();
-  // tile epilogue
+  // tile epilogue: node j of the window takes count(j) one - sumF(j) from slot j and
+  // sumF(j - 1) from slot j - 1
   if (!r.tail) {
-    real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (W + 1);
-    for (int k = tid; k <= W; k += kWG) {
-      real sum = sh.dep[0][k];
+    unsigned long long GM* part = s.partial + static_cast<size_t>(tile) * (W + 1);
+    const uint32_t GM* hrow = s.hist + static_cast<size_t>(tile) * kWaves * W;
+    for (int j = tid; j <= W; j += kWG) {
+      unsigned long long v = 0ull;
+      if (j < W) {
+        uint32_t cnt = 0u;
+        if (r.fine) {
+          cnt = sh.cnt[j];
+        } else {
 #pragma unroll
-      for (int c = 1; c < kCopies; ++c) sum += sh.dep[c][k];
-      part[k] = sum;
+          for (int w = 0; w < kWaves; ++w) cnt += hrow[w * W + j];
+        }
+        unsigned long long f = 0ull;
+#pragma unroll
+        for (int c = 0; c < kDepCopies; ++c) f += sh.dep[c][j];
+        v = static_cast<unsigned long long>(cnt) * s.dep_one - f;
+      }
+      if (j > 0) {
+#pragma unroll
+        for (int c = 0; c < kDepCopies; ++c) v += sh.dep[c][j - 1];
+      }
+      part[j] = v;
     }
   }
   if (tid == 0) {
     if (sh.err) atomicOr(sim.error, sh.err);
-    if (sh.abs_cnt[0]) atomicAdd(&s.absorbed[0], static_cast<unsigned long long>(sh.abs_cnt[0]));
-    if (sh.abs_cnt[1]) atomicAdd(&s.absorbed[1], static_cast<unsigned long long>(sh.abs_cnt[1]));
-    if (sh.abs_cnt[0]) atomicAdd(&s.absorbed_energy[0], sh.abs_e[0]);
-    if (sh.abs_cnt[1]) atomicAdd(&s.absorbed_energy[1], sh.abs_e[1]);
+    TileStats ts{};
+    for (int w = 0; w < kWaves; ++w) {  // waves in order
+      ts.ke += sh.wst[w][0];
+      ts.mom += sh.wst[w][1];
+      ts.abs_e[0] += sh.wst[w][2];
+      ts.abs_e[1] += sh.wst[w][3];
+      ts.abs_n[0] += sh.wcnt[w][0];
+      ts.abs_n[1] += sh.wcnt[w][1];
+      ts.emit[0] += sh.wcnt[w][2];
+      ts.emit[1] += sh.wcnt[w][3];
+      ts.refl[0] += sh.wcnt[w][4];
+      ts.refl[1] += sh.wcnt[w][5];
+    }
+    s.tstats[tile] = ts;
   }
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG)
@@ -1309,7 +1577,7 @@ __global__ __launch_bounds__(kWG) void k_main(const SimDev* __restrict__ simp) {
 //   once per pass, however few lanes it has.
 // k_main stored each candidate's post-push state beside its sorted slot; the
 // post-collision velocity is written to that slot.  Births (electron ionization) are
-// staged in the order of their parents (= input order) and deposited; k_finalize appends
+// staged in the order of their parents (= input order); k_finalize appends and deposits
 // them.
 // ====================================================================================
 template <class P>
@@ -1364,11 +1632,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   const RecPtr out = rec_buf(&sim.sp[cw.x], pq);
   const RecPtr stage_e = rec_stage(&sim.sp[cw.x], 0);
   const RecPtr stage_i = rec_stage(&sim.sp[cw.x], 1);
-  const SpeciesDev ion = sim.sp[electrons ? cw.x + 1 : cw.x];  // used by electron tiles
-  real GM* part = static_cast<real GM*>(s.partial) + static_cast<size_t>(tile) * (s.W + 1);
   for (uint32_t b = 0; b < n; b += kWG) {
     const uint32_t e = b + tid;
     bool born = false;
+    uint32_t parent = 0u;
     int d = 0;
     real pos = real(0);
     real vs[3] = {real(0), real(0), real(0)}, vi[3] = {real(0), real(0), real(0)};
@@ -1395,6 +1662,7 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
           sto<real>(out.f[F_VY], o, v[1]);
           sto<real>(out.f[F_VZ], o, v[2]);
           born = s.sp == 0 && ch == 3;
+          parent = c.y;
         }
       }
     }
@@ -1408,18 +1676,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     if (born) {
       const uint32_t si = r.lo + births + pre;
       if (si < s.cap) {
+        // (deposited by k_finalize once it is known that the birth fits)
         store_record<P, false>(stage_e, si, d, pos, vs[0], vs[1], vs[2], 0u);
         store_record<P, false>(stage_i, si, d, pos, vi[0], vi[1], vi[2], 0u);
-        const int k = r.tail ? -1 : window_slot(s, tile, d);
-        if (k >= 0) {
-          real w0, w1;
-          deposit_weights<P>(pos, w0, w1);
-          atomicAdd(&part[k], w0);
-          atomicAdd(&part[k + 1], w1);
-        } else {
-          far_deposit<P>(s, d, pos);
-        }
-        far_deposit<P>(ion, d, pos);
+        if (s.mode == kModeFine) s.fpid[si] = parent;  // fine sort: ids by parent id
       } else {
         atomicOr(sim.error, kErrState);
       }
@@ -1436,20 +1696,88 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   }
 }
 // ====================================================================================
+// k_emit: secondary emission (Sec. 2: electrons inserted at the boundaries).  One wave per
+// ion tile walks the absorbed-ion lists k_main left in its (tile, wave) units: an ion emits
+// iff word 0 of its Philox block 6 is below floor(gamma 2^32) and the electron's start
+// position (blocks 7, 8; device_common.h, emitted_electron) is inside the box.  The
+// electrons are stored compacted in list order at the front of the unit's list range, and
+// each unit's count goes to k_birth_scan, which numbers them after the ionisation births.
+// ====================================================================================
+template <class P>
+__global__ __launch_bounds__(kWG) void k_emit(const SimDev* __restrict__ simp) {
+  using real = typename Part<P>::real;
+  const SimDev& sim = *simp;
+  const int g = blockIdx.x * kWaves + wave_id();  // one wave per tile
+  if (g >= sim.total_tiles) return;
+  const int2 tt = sim.tile_table[g];
+  const SpeciesDev s = sim.sp[tt.x];
+  if (!s.t_see) return;
+  const uint32_t step32 = static_cast<uint32_t>(*sim.step);
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = lanes_below();
+  RecPtr out;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.f[k] = s.em_stage[k];
+  out.boff4 = out.boff8 = 0u;
+  uint32_t n_wall[2] = {0u, 0u};
+  for (int w = 0; w < kWaves; ++w) {
+    const int unit = tt.y * kWaves + w;
+    const uint32_t n = s.ab_cnt[unit], lo = s.em_lo[unit];
+    uint32_t em = 0u;  // wave-uniform
+    for (uint32_t b = 0; b < n; b += 64u) {
+      const uint32_t k = b + static_cast<uint32_t>(lane);
+      bool emit = false;
+      int st = 0;
+      double xe = 0.0, ve[3] = {0.0, 0.0, 0.0};
+      if (k < n && lo + k < s.cap) {
+        const uint2 a = s.ab_list[lo + k];
+        st = static_cast<int>(a.y);
+        if (philox(a.x, step32, 6u, 0u, s.key0, s.key1).x < s.t_see)
+          emit = emitted_electron(s.n_cells, st, s.vth_see,
+                                  philox(a.x, step32, 7u, 0u, s.key0, s.key1),
+                                  philox(a.x, step32, 8u, 0u, s.key0, s.key1), xe, ve);
+      }
+      const unsigned long long m = __ballot(emit);
+      if (emit) {
+        const uint32_t e = lo + em + static_cast<uint32_t>(__popcll(m & lt));
+        const double c = floor(xe);
+        if constexpr (std::is_same<P, P32>::value)
+          store_record<P, false>(out, e, static_cast<int>(c), __double2float_rz(xe - c),
+                                 static_cast<float>(ve[0]), static_cast<float>(ve[1]),
+                                 static_cast<float>(ve[2]), 0u);
+        else
+          store_record<P, false>(out, e, static_cast<int>(c), xe, static_cast<real>(ve[0]),
+                                 static_cast<real>(ve[1]), static_cast<real>(ve[2]), 0u);
+      }
+      em += static_cast<uint32_t>(__popcll(m));
+      n_wall[0] += static_cast<uint32_t>(__popcll(__ballot(emit && st == 1)));
+      n_wall[1] += static_cast<uint32_t>(__popcll(__ballot(emit && st == 2)));
+    }
+    if (lane == 0) s.em_cnt[unit] = em;
+  }
+  if (lane == 0) {
+    s.tstats[tt.y].emit[0] = n_wall[0];
+    s.tstats[tt.y].emit[1] = n_wall[1];
+  }
+}
+
+// ====================================================================================
 // Births are appended after the sorted survivors in the order of their parents' input
 // index (the electron tiles are in index order and each keeps its births in index
 // order); the children take the next ids of their species.
 // k_birth_scan (one workgroup per discharge) scans the electron tiles' birth counts,
 // settles how many births fit and their first id, and advances the step counter;
 // k_finalize (one wave per tile, all tiles) copies each electron tile's staged births --
-// electrons and ions -- to their places.
+// electrons and ions -- to their places and deposits those that fit (a birth dropped for
+// want of capacity leaves no charge behind).
 // ====================================================================================
 __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restrict__ simp) {
   const SimDev& sim = *simp;
   const DischargeDev dd = sim.ds[blockIdx.x];
   const SpeciesDev se = sim.sp[dd.spec0];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
-  const int q = static_cast<int>((*sim.step + 1ull) & 1ull);
+  const unsigned long long step = *sim.step;
+  const int q = static_cast<int>((step + 1ull) & 1ull);
   const int nt = se.n_tiles + se.n_tail;
   // thread s (s < 2) settles species s: its counters are loaded before the scan, so their
   // latency overlaps it (nothing in this kernel writes them before they are used)
@@ -1461,10 +1789,19 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     n_prev = s.n_total[q ^ 1];
   }
   const uint32_t B = array_exclusive_scan_to(se.birth_cnt, se.birth_base, nt, lds);
+  // electrons emitted by absorbed ions follow the ionisation births, in the order of their
+  // parent ions' input index ((tile, wave) units in order, each list in input order)
+  const SpeciesDev sion = sim.sp[dd.spec0 + 1];
+  const int nu_i = (sion.n_tiles + sion.n_tail) * kWaves;
+  uint32_t E = 0u;
+  if (sion.t_see) E = array_exclusive_scan_to(sion.em_cnt, sion.em_base, nu_i, lds);
   if (threadIdx.x < 2) {
     const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
-    if (threadIdx.x == 0) se.birth_base[nt] = B;
-    uint32_t fit = B;
+    if (threadIdx.x == 0) {
+      se.birth_base[nt] = B;
+      if (sion.t_see) sion.em_base[nu_i] = E;
+    }
+    uint32_t fit = threadIdx.x == 0 ? B + E : B;
     const uint32_t room = s.cap > n_surv ? s.cap - n_surv : 0u;
     if (fit > room) {
       fit = room;
@@ -1481,10 +1818,74 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     *s.next_id = nid + fit;
     *s.births += fit;
   }
+  // The step's per-tile sums of both species, combined in a fixed order (each thread over
+  // its tiles in order, a butterfly inside each wave, then the waves in order): the
+  // cumulative wall tallies and, on energy steps, the kinetic energies and momentum.
+  constexpr int kD = 4, kU = 6;
+  __shared__ double wd[2][kSolveWG / 64][kD];
+  __shared__ uint32_t wu[2][kSolveWG / 64][kU];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int sp = 0; sp < 2; ++sp) {
+    const SpeciesDev s = sim.sp[dd.spec0 + sp];
+    const int ntiles = s.n_tiles + s.n_tail;
+    double d[kD] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t u[kU] = {0u, 0u, 0u, 0u, 0u, 0u};
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+      const TileStats ts = s.tstats[t];
+      d[0] += ts.ke;
+      d[1] += ts.mom;
+      d[2] += ts.abs_e[0];
+      d[3] += ts.abs_e[1];
+      u[0] += ts.abs_n[0];
+      u[1] += ts.abs_n[1];
+      u[2] += ts.emit[0];
+      u[3] += ts.emit[1];
+      u[4] += ts.refl[0];
+      u[5] += ts.refl[1];
+    }
+#pragma unroll
+    for (int k = 0; k < kD; ++k) d[k] = wave_sum(d[k]);
+#pragma unroll
+    for (int k = 0; k < kU; ++k) u[k] = wave_sum(u[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < kD; ++k) wd[sp][wv][k] = d[k];
+#pragma unroll
+      for (int k = 0; k < kU; ++k) wu[sp][wv][k] = u[k];
+    }
+  }
   // The last discharge's workgroup advances the step counter (every workgroup read it at
   // its start); the kernel boundary publishes it to k_finalize and the next step.
   __syncthreads();
   if (threadIdx.x == 0) {
+    const bool energy = diag_step(dd, step);
+    double mom = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesDev s = sim.sp[dd.spec0 + sp];
+      double d[kD] = {0.0, 0.0, 0.0, 0.0};
+      unsigned long long u[kU] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+        for (int k = 0; k < kD; ++k) d[k] += wd[sp][w][k];
+        for (int k = 0; k < kU; ++k) u[k] += wu[sp][w][k];
+      }
+      s.absorbed[0] += u[0];
+      s.absorbed[1] += u[1];
+      s.absorbed_energy[0] += d[2];
+      s.absorbed_energy[1] += d[3];
+      s.emitted[0] += u[2];
+      s.emitted[1] += u[3];
+      s.reflected[0] += u[4];
+      s.reflected[1] += u[5];
+      if (energy) {
+        const double ak = fabs(s.kappa);
+        dd.dstat[DS_KIN_E + sp] = d[0] / (2.0 * ak);
+        mom += d[1] / ak;
+      }
+    }
+    if (energy) {
+      dd.dstat[DS_MOM] = mom;
+      *dd.energy_step = step;
+    }
     const uint32_t done = atomicAdd(sim.fin_count, 1u);
     if (done == gridDim.x - 1u) {
       *sim.fin_count = 0u;
@@ -1503,7 +1904,9 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
   if (g < sim.total_tiles) {
     const int2 tt = sim.tile_table[g];
     const SpeciesDev se = sim.sp[tt.x];
-    if (se.sp == 0) {
+    if (se.mode == kModeFine) {
+      // births of a fine-sorted species go to their sorting cells (k_fine_births)
+    } else if (se.sp == 0) {
       const int u = tt.y;
       const uint32_t b0 = se.birth_base[u], b1 = se.birth_base[u + 1];
       const uint32_t first = se.stage_first[u];
@@ -1528,6 +1931,41 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
           }
           store_record<P>(dst, n_surv + b, cell, pos, ldg<real>(src.f[F_VX], si),
                           ldg<real>(src.f[F_VY], si), ldg<real>(src.f[F_VZ], si), nid + b);
+          if constexpr (std::is_same<P, P64>::value) cell = static_cast<int>(floor(pos));
+          if (cell >= 0 && cell < s.n_cells) far_deposit<P>(s, cell, pos);
+        }
+      }
+    } else if (se.t_see) {
+      // an ion tile's emitted electrons, after all ionisation births
+      const int u = tt.y;
+      const SpeciesDev el = sim.sp[tt.x - 1];
+      const uint32_t B = el.birth_base[el.n_tiles + el.n_tail];
+      const uint32_t fit = el.fin[0], nid = el.fin[1];
+      const uint32_t n_surv = el.n_sorted[q];
+      RecPtr src;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) src.f[k] = se.em_stage[k];
+      src.boff4 = src.boff8 = 0u;
+      const RecPtr dst = rec_buf(&sim.sp[tt.x - 1], q);
+      for (int w = 0; w < kWaves; ++w) {
+        const int unit = u * kWaves + w;
+        const uint32_t cnt = se.em_cnt[unit], lo = se.em_lo[unit], base = se.em_base[unit];
+        for (uint32_t k = static_cast<uint32_t>(lane); k < cnt; k += 64u) {
+          const uint32_t b = B + base + k;
+          const uint32_t si = lo + k;
+          if (b >= fit || si >= se.cap) continue;
+          int cell = 0;
+          real pos;
+          if constexpr (std::is_same<P, P32>::value) {
+            cell = ldg<int>(src.f[F32_CELL], si);
+            pos = ldg<float>(src.f[F32_OFF], si);
+          } else {
+            pos = ldg<double>(src.f[F64_X], si);
+            cell = static_cast<int>(floor(pos));
+          }
+          store_record<P>(dst, n_surv + b, cell, pos, ldg<real>(src.f[F_VX], si),
+                          ldg<real>(src.f[F_VY], si), ldg<real>(src.f[F_VZ], si), nid + b);
+          if (cell >= 0 && cell < el.n_cells) far_deposit<P>(el, cell, pos);
         }
       }
     }
@@ -1554,8 +1992,7 @@ static void launch(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e
 void launch_combine(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
   const dim3 grid(li.n_node_wgs), block(kCombineNodes * kCombineLanes);
-  if (li.fp32) launch(k_combine<float>, grid, block, st, e0, e1, sim);
-  else launch(k_combine<double>, grid, block, st, e0, e1, sim);
+  launch(k_combine, grid, block, st, e0, e1, sim);
 }
 
 void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStream_t st,
@@ -1572,8 +2009,11 @@ void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 
 void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
-  launch(k_scan_cells, dim3(li.n_cell_wgs), dim3(kScanCells * kScanLanes), st, e0,
-         static_cast<hipEvent_t>(nullptr), sim);
+  if (li.n_cell_wgs > 0)
+    launch(k_scan_cells, dim3(li.n_cell_wgs), dim3(kScanCells * kScanLanes), st, e0,
+           static_cast<hipEvent_t>(nullptr), sim);
+  else if (e0)
+    (void)hipEventRecord(e0, st);  // every species unsorted: no per-cell offsets
   launch(k_scan_base, dim3(li.n_spec), dim3(kSolveWG), st, static_cast<hipEvent_t>(nullptr),
          e1, sim);
 }
@@ -1587,8 +2027,14 @@ void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                     hipEvent_t e1) {
   const dim3 grid(li.n_collide_wgs);
-  if (li.fp32) launch(k_collide<P32>, grid, dim3(kWG), st, e0, e1, sim);
-  else launch(k_collide<P64>, grid, dim3(kWG), st, e0, e1, sim);
+  hipEvent_t e1c = li.emission ? static_cast<hipEvent_t>(nullptr) : e1;
+  if (li.fp32) launch(k_collide<P32>, grid, dim3(kWG), st, e0, e1c, sim);
+  else launch(k_collide<P64>, grid, dim3(kWG), st, e0, e1c, sim);
+  if (li.emission) {
+    const dim3 eg((li.total_tiles + kWaves - 1) / kWaves);
+    if (li.fp32) launch(k_emit<P32>, eg, dim3(kWG), st, static_cast<hipEvent_t>(nullptr), e1, sim);
+    else launch(k_emit<P64>, eg, dim3(kWG), st, static_cast<hipEvent_t>(nullptr), e1, sim);
+  }
 }
 
 void launch_finalize(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,

@@ -71,6 +71,37 @@ int largest_divisor_at_most(int n, int c) {
 double electron_mass() { return kMe; }
 double ion_mass(const pic_config& c) { return c.mass_i_amu * kAmu; }
 
+// Coulomb pair coefficients e^4 lnLambda dt / (8 pi eps0^2 m_ab^2) [SI] of e-e, i-i and e-i
+// pairs (m_ab the reduced mass of the pair).
+void coulomb_coefficients(const pic_config& c, double coef[3]) {
+  const double me = kMe, mi = ion_mass(c);
+  const double mab[3] = {0.5 * me, 0.5 * mi, me * mi / (me + mi)};
+  for (int k = 0; k < 3; ++k)
+    coef[k] = (kQe * kQe) * (kQe * kQe) * c.coulomb_log * c.dt_s /
+              (8.0 * (kTwoPiH / 2.0) * kEps0 * kEps0 * mab[k] * mab[k]);
+}
+
+// A probability as the threshold of a 32-bit Philox word: the event happens iff the word
+// is below floor(p 2^32) (p >= 1: always, except for the word 2^32 - 1).
+uint32_t word_threshold(double p) {
+  if (!(p > 0.0)) return 0u;
+  const double t = std::floor(p * 4294967296.0);
+  return t >= 4294967295.0 ? 4294967295u : static_cast<uint32_t>(t);
+}
+
+// Spread sqrt(e T / m_e) of each velocity component of the secondary electrons, in cells
+// per step.
+double see_spread(const pic_config& c, const pic_derived& k) {
+  return std::sqrt(c.see_te_ev * kQe / kMe) / k.vunit;
+}
+
+// Series capacitance in the units of the normalised field equations (eps0 A / dx per
+// electrode area A), 0 for the ideal source or a periodic box.
+double circuit_cap_norm(const pic_config& c, const pic_derived& k) {
+  if (!(c.circuit_cap_f_m2 > 0.0) || c.periodic) return 0.0;
+  return c.circuit_cap_f_m2 * k.dx / kEps0;
+}
+
 int validate_config(const pic_config& c, std::string* why) {
   auto bad = [&](const char* m) {
     *why = m;
@@ -95,6 +126,28 @@ int validate_config(const pic_config& c, std::string* why) {
   if (c.eedf_bins > 256) return bad("eedf_bins > 256");
   if (c.eedf_bins > 0 && !(c.eedf_max_ev > 0)) return bad("eedf_max_ev");
   if (c.xsec_model == PIC_XS_CONST_E_ELASTIC && !(c.eps_cap_ev > 0)) return bad("eps_cap_ev");
+  if (c.sort_mode > PIC_SORT_FINE) return bad("sort_mode");
+  if (c.sort_mode == PIC_SORT_FINE) {
+    if (c.see_gamma > 0.0) return bad("secondary emission is not built for PIC_SORT_FINE");
+    if (c.sort_cell_capacity > static_cast<uint32_t>(kMaxFineSlots))
+      return bad("sort_cell_capacity > 65536");
+    for (int sp = 0; sp < 2; ++sp) {
+      const uint32_t g = c.cells_per_tile[sp] > 0 ? c.cells_per_tile[sp]
+                                                  : (c.sort_cell_cells > 0 ? c.sort_cell_cells : 2);
+      if (c.periodic && c.n_cells % g != 0)
+        return bad("periodic fine sort: the sorting cell size must divide n_cells");
+    }
+  }
+  if (c.coulomb > 7) return bad("coulomb: bits 0-2 only");
+  if (c.coulomb != 0 && c.sort_mode != PIC_SORT_COUNTING)
+    return bad("coulomb collisions pair the particles of a cell: need PIC_SORT_COUNTING");
+  if (c.coulomb != 0 && !(c.coulomb_log > 0.0)) return bad("coulomb_log must be > 0");
+  if (!(c.see_gamma >= 0.0 && c.see_gamma <= 1.0)) return bad("see_gamma must be in [0, 1]");
+  if (!(c.refl_e >= 0.0 && c.refl_e <= 1.0)) return bad("refl_e must be in [0, 1]");
+  if (c.see_gamma > 0.0 && !(c.see_te_ev > 0.0)) return bad("see_te_ev must be > 0");
+  if ((c.see_gamma > 0.0 || c.refl_e > 0.0) && c.periodic)
+    return bad("electrode processes need a bounded discharge");
+  if (!(c.circuit_cap_f_m2 >= 0.0)) return bad("circuit_cap_f_m2 must be >= 0");
   return PIC_OK;
 }
 
@@ -149,6 +202,42 @@ void choose_tiles(const pic_config& c, const pic_derived& k, TileChoice tc[2]) {
   const uint64_t n0[2] = {c.n_e0, c.n_i0};
   const int d_default[2] = {32, 4};
   for (int s = 0; s < 2; ++s) {
+    tc[s].nmax = 0;
+    if (c.sort_mode == PIC_SORT_FINE) {
+      // the paper's sorting cells: G grid cells each (N_gc = G + 1 grid points), nmax
+      // slots each (default: 2.5 times the load's mean count of the species per sorting
+      // cell, plus 64, in whole wavefronts)
+      // (cells_per_tile, a tuning field, may set it per species)
+      const int g0 = c.cells_per_tile[s] > 0 ? static_cast<int>(c.cells_per_tile[s])
+                                             : (c.sort_cell_cells > 0 ? static_cast<int>(c.sort_cell_cells) : 2);
+      const int G = std::max(1, std::min(g0, std::min(kMaxCellsPerTile, N)));
+      const uint64_t n0s = s == 0 ? c.n_e0 : c.n_i0;
+      int nmax = static_cast<int>(c.sort_cell_capacity);
+      if (nmax <= 0) {
+        const double mean = static_cast<double>(n0s) * G / N;
+        nmax = static_cast<int>(std::ceil((2.5 * mean + 64.0) / 64.0)) * 64;
+      }
+      tc[s].C = G;
+      tc[s].D = std::max(0, std::min(c.window[s] > 0 ? static_cast<int>(c.window[s]) : d_default[s],
+                                     (kMaxWindow - G) / 2));
+      if (c.periodic) tc[s].D = std::max(0, std::min(tc[s].D, (N - 2 * G - 1) / 2));
+      tc[s].W = G + 2 * tc[s].D;
+      tc[s].n_tiles = (N + G - 1) / G;
+      tc[s].n_tail = 0;
+      tc[s].nmax = nmax;
+      continue;
+    }
+    if (c.sort_mode == PIC_SORT_NONE) {
+      // unsorted: the array is cut into equal index ranges (tail-like tiles), about 2048
+      // particles of the capacity each; no cell windows
+      const uint64_t cap = s == 0 ? c.capacity_e : c.capacity_i;
+      tc[s].C = 1;
+      tc[s].D = 0;
+      tc[s].W = 1;
+      tc[s].n_tiles = static_cast<int>(std::max<uint64_t>(1, std::min<uint64_t>(65536, (cap + 2047) / 2048)));
+      tc[s].n_tail = 0;
+      continue;
+    }
     int C;
     if (c.cells_per_tile[s] > 0) {
       C = static_cast<int>(c.cells_per_tile[s]);

@@ -43,6 +43,7 @@ constexpr int kScanCells = 16;       // cells of a k_scan_cells workgroup (256 t
 constexpr int kMaxCells = 16384;     // LDS histogram of the general (initial) sort
 constexpr int kMaxEedfBins = 256;
 constexpr int kMaxCellsPerTile = 64;
+constexpr int kMaxFineSlots = 65536; // slots of one fine-sort sorting cell (LDS bit masks)
 
 enum ErrorBits : uint32_t {
   kErrCapacity = 1u,     // births did not fit the particle arrays
@@ -50,14 +51,45 @@ enum ErrorBits : uint32_t {
   kErrIdOverflow = 4u,   // particle ids would pass 2^32 - 1
   kErrFarGroup = 8u,     // too many far movers into one cell in one step
   kErrState = 16u,       // inconsistent device state (an index out of range was refused)
+  kErrNonfinite = 32u,   // a particle's position was not finite or not in a cell
+};
+
+// Per-tile partial sums of one step, combined over the tiles of a species in a fixed
+// order by k_birth_scan (so the totals do not depend on the order tiles finish in).
+struct TileStats {
+  double ke;          // sum of (v_x^2(n-1/2) + v_x^2(n+1/2)) / 2 + v_y^2 + v_z^2 (energy steps)
+  double mom;         // sum of v_x(n+1/2) (energy steps)
+  double abs_e[2];    // energy of the particles absorbed at each wall [eV]
+  uint32_t abs_n[2];  // particles absorbed at each wall
+  uint32_t emit[2];   // secondary electrons emitted at each wall (ion species)
+  uint32_t refl[2];   // electrons reflected at each wall (electron species)
+  uint32_t pad[2];
+};
+
+// Per-discharge results of the last step, normalised units (energy Q^2 dx / (eps0 A),
+// charge Q / A, potential Q dx / (eps0 A)).
+enum : int {
+  DS_KIN_E = 0,     // kinetic energy of the electrons (energy steps)
+  DS_KIN_I = 1,     // kinetic energy of the ions (energy steps)
+  DS_MOM = 2,       // x-momentum sum_s sum v_x / |kappa_s| (energy steps)
+  DS_FIELD = 3,     // field energy 1/2 sum over cells of (Phi_j - Phi_j+1)^2
+  DS_SUM_RHO = 4,   // net node charge sum_j (w_i - w_e)
+  DS_PHI0 = 5,      // potential of the driven electrode
+  DS_Q = 6,         // charge of the driven electrode's conductor (series capacitor)
+  DS_Q_INIT = 7,    // that charge at the load
+  DS_N = 8
 };
 
 // Per-particle record fields of the two layouts.
 enum : int { F32_CELL = 0, F32_OFF = 1, F_VX = 2, F_VY = 3, F_VZ = 4, F_ID = 5 };
 enum : int { F64_X = 0 };
 
+// Array order a species keeps (pic_sort).
+enum : int32_t { kModeCounting = 0, kModeNone = 1, kModeFine = 2 };
+
 struct SpeciesDev {
   int32_t ds, sp, n_cells, periodic;
+  int32_t mode;                // kMode*: counting sort, unsorted (range tiles), fine sort
   int32_t C, D, W, n_tiles;        // cell tiles: tile t owns cells [tC, tC + C)
   int32_t n_tail;                  // tail tiles: the unsorted births at the end of the array
   int32_t n_nodes;
@@ -79,8 +111,10 @@ struct SpeciesDev {
   uint32_t GM* tilerel;        // [n_tiles * kWaves * W] offset of (tile, wave) in cell c from base[c]
   uint32_t GM* thist;          // [n_tail * kWaves * n_cells] post-push cell counts per tail row
   uint32_t GM* trel;           // [n_tail * kWaves * n_cells] running offset of a tail row in cell c
-  void GM* partial;            // [n_tiles * (W + 1)] tile deposit windows (float or double)
-  double GM* far_w;            // [n_nodes] deposits of far movers and births
+  // Charge deposits are integers: a weight w in [0, 1] is added as round(w 2^dep_shift),
+  // so sums are exact and do not depend on the order of the additions.
+  unsigned long long GM* partial;  // [n_tiles * (W + 1)] tile deposit windows
+  unsigned long long GM* far_w;    // [n_nodes] deposits of far movers, tail tiles and births
   uint32_t GM* far_count;      // [1]
   uint4 GM* far_list;          // [far_cap] far movers of the cell tiles: (cell, index, tile, 0)
   uint4 GM* far_grouped;       // [far_cap] far list grouped by cell
@@ -102,8 +136,13 @@ struct SpeciesDev {
   double GM* absorbed_energy;        // [2] eV
   unsigned long long GM* births;     // [1]
   unsigned long long GM* collisions; // [3]
-  double GM* ke_sum;                 // [4] sum vx^2, vy^2, vz^2, vx (diagnostic steps)
+  unsigned long long GM* emitted;    // [2] secondary electrons emitted per wall (ions)
+  unsigned long long GM* reflected;  // [2] electrons reflected per wall (electrons)
   unsigned long long GM* psteps;     // [1] particles stepped, summed over steps
+  TileStats GM* tstats;              // [n_tiles + n_tail] this step's per-tile sums
+  // fixed-point deposit: one = 2^dep_shift, inv = 2^-dep_shift
+  unsigned long long dep_one;
+  double dep_scale, dep_inv;
   // physics (normalised units)
   double kappa;
   float kappa_f;
@@ -112,6 +151,31 @@ struct SpeciesDev {
   uint32_t key0, key1;
   int32_t xsec;
   double sigma_const;
+  // electrode processes: reflection threshold (electrons) and emission threshold (ions) of
+  // a Philox word, and the spread of the emitted electrons' velocity components
+  uint32_t t_refl, t_see;
+  double vth_see;
+  // secondary emission (ion species): k_main lists the absorbed ions (id, wall status) in
+  // their (tile, wave) unit's index range, in input order; k_emit stores the emitted
+  // electrons (electron records in the fields of `fld`) compacted at the front of the same
+  // range.  Per (tile, wave): absorbed count, first list index, emitted count and (after
+  // k_birth_scan) the exclusive scan of the emitted counts
+  uint2 GM* ab_list;           // [cap]
+  void GM* em_stage[6];        // [cap] each
+  uint32_t GM* ab_cnt;         // [(n_tiles + n_tail) * kWaves]
+  uint32_t GM* em_lo;          // [(n_tiles + n_tail) * kWaves]
+  uint32_t GM* em_cnt;         // [(n_tiles + n_tail) * kWaves]
+  uint32_t GM* em_base;        // [(n_tiles + n_tail) * kWaves + 1]
+  // fine sort (the paper's fixed-capacity sorting cells, kModeFine): sorting cell k (the
+  // tile k, C grid cells) holds its particles in slots [k nmax, k nmax + fcnt[k]) of the
+  // `fine` arrays (fields as in fld), sorted in place every step; its free slots at the end
+  // park the particles that leave it (flv of them) until they are moved
+  void GM* fine[6];
+  uint32_t nmax;
+  uint32_t GM* fcnt;           // [n_tiles]
+  uint32_t GM* flv;            // [n_tiles]
+  uint32_t GM* fpid;           // [cap] parent id of each staged birth (electron species)
+  uint32_t GM* fpid_list;      // [cap] the step's birth parent ids in birth order
   uint32_t GM* gsort_hist;     // [n_gtiles * n_cells] general sort scratch (initial sort)
   // initial load
   uint32_t n_init;
@@ -127,14 +191,22 @@ struct DischargeDev {
   float GM* E32;
   double GM* acc_w[2];
   double GM* acc_phi;
-  double GM* scratch;          // [n_nodes] solver scratch
+  double GM* dstat;            // [DS_N] results of the last step
+  unsigned long long GM* energy_step;  // step of the last kinetic-energy sums
   unsigned long long GM* acc_count;
   unsigned long long GM* eedf;          // [eedf_bins + 1]
   unsigned long long GM* eedf_samples;
   int32_t eedf_bins, diag_every;
   double eedf_inv_width;
   double vhat_amp, phase_per_step;
+  double cap_norm;             // series capacitance in units of eps0 A / dx; 0: ideal source
   int64_t avg_start;
+  // binary Coulomb collisions in a cell: bit 0 e-e, bit 1 i-i, bit 2 e-i
+  int32_t coulomb;
+  double coul_coef[3];         // e^4 lnLambda dt / (8 pi eps0^2 m_ab^2) of e-e, i-i, e-i [SI]
+  double coul_dens;            // density of one macro-particle per cell [m^-3]
+  double vunit;                // dx / dt [m/s]
+  double mfrac_e, mfrac_i;     // an e-i pair's shares of the change: m_i / M, m_e / M
 };
 
 struct SimDev {
