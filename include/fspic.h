@@ -106,10 +106,16 @@ enum pic_sort {
                             result, canonical order) */
   PIC_SORT_NONE = 1,     /* unsorted: survivors keep their order, the deposit adds straight
                             into the node array (the unsorted GPU variant of Sec. 3.2) */
-  PIC_SORT_FINE = 2      /* the paper's in-place sort into fixed-capacity sorting cells
+  PIC_SORT_FINE = 2,     /* the paper's in-place sort into fixed-capacity sorting cells
                             (Sec. 3.2 data structure, Sec. 3.7 steps 1a/1b, 2 and 3); the
                             order inside a sorting cell is not fixed, so births take their
                             ids in increasing parent id */
+  PIC_SORT_LAG = 3       /* the counting sort keyed on the cell a particle occupied at the
+                            start of the step (known before the push), so the pre-pass reads
+                            only that field; the array is sorted with a lag of one step, and a
+                            particle absorbed in the step leaves a dead record that the next
+                            step skips (pic_get_state and pic_diagnostics leave them out);
+                            every discharge of a simulation or none */
 };
 
 /* Normalised constants the library derives from a pic_config (Sec. 3.3). */

@@ -126,14 +126,15 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-SORT_MODES = ("counting", "fine", "none")
+SORT_MODES = ("counting", "fine", "none", "lag")
 
 
 def params_from(wl, fp32_offset=False):
     """Oracle parameters of a workload.  The array order the oracle keeps follows the
     workload's sort mode: sorted by cell for the counting and the fine (paper) sort, input
-    order for the unsorted variant; under the fine sort, whose order inside a sorting cell
-    is not fixed, births take ids in increasing parent id."""
+    order for the unsorted variant, by the start-of-step cell for the lagged counting sort;
+    under the fine sort, whose order inside a sorting cell is not fixed, births take ids in
+    increasing parent id."""
     p = OrcParams()
     mode = wl.get("sort_mode", "counting")
     assert mode in SORT_MODES, mode
@@ -145,7 +146,7 @@ def params_from(wl, fp32_offset=False):
         elif name == "fp32_offset":
             p.fp32_offset = 1 if fp32_offset else 0
         elif name == "sort_mode":
-            p.sort_mode = 1 if mode == "none" else 0
+            p.sort_mode = {"none": 1, "lag": 2}.get(mode, 0)
         elif name == "birth_rank":
             p.birth_rank = 1 if mode == "fine" else 0
         else:

@@ -38,6 +38,7 @@ struct orc_sim {
     double *tx, *tvx, *tvy, *tvz;
     uint32_t* tid;
     int32_t *flags, *cell;
+    int32_t* start_cell[2];   /* cell of each particle at the start of the step */
     int64_t* perm;
     double *bx[2], *bvx[2], *bvy[2], *bvz[2];
     /* grid */
@@ -508,6 +509,7 @@ orc_sim* orc_create(const orc_params* p, int64_t cap_e, int64_t cap_i) {
         s->bvy[sp] = (double*)xcalloc(c, sizeof(double));
         s->bvz[sp] = (double*)xcalloc(c, sizeof(double));
         s->w[sp] = (double*)xcalloc((size_t)s->n_nodes, sizeof(double));
+        s->start_cell[sp] = (int32_t*)xcalloc(c, sizeof(int32_t));
         s->acc_w[sp] = (double*)xcalloc((size_t)s->n_nodes, sizeof(double));
     }
     s->tx = (double*)xcalloc((size_t)cmax, sizeof(double));
@@ -541,7 +543,7 @@ void orc_destroy(orc_sim* s) {
         free(s->w[sp]); free(s->acc_w[sp]);
     }
     free(s->tx); free(s->tvx); free(s->tvy); free(s->tvz); free(s->tid);
-    free(s->flags); free(s->cell); free(s->perm);
+    free(s->flags); free(s->cell); free(s->start_cell[0]); free(s->start_cell[1]); free(s->perm);
     free(s->rho); free(s->phi); free(s->ef); free(s->acc_phi); free(s->eedf);
     free(s->bparent); free(s->bkey_perm);
     free(s);
@@ -554,11 +556,15 @@ int orc_get_consts(const orc_sim* s, orc_consts* out) {
 
 int64_t orc_count(const orc_sim* s, int sp) { return s->n[sp]; }
 
-/* Re-order species sp by a stable sort on cell = floor(x) (input order breaks ties). */
-static void sort_species(orc_sim* s, int sp) {
+/* Re-order species sp by a stable sort on `key` (input order breaks ties); with key NULL
+   the key is the cell the particle is in, floor(x). */
+static void sort_species_by(orc_sim* s, int sp, const int32_t* key) {
     int64_t n = s->n[sp];
-    for (int64_t i = 0; i < n; ++i) s->cell[i] = (int32_t)floor(s->x[sp][i]);
-    orc_stable_sort_by_cell(n, s->cell, s->p.n_cells, s->perm);
+    if (!key) {
+        for (int64_t i = 0; i < n; ++i) s->cell[i] = (int32_t)floor(s->x[sp][i]);
+        key = s->cell;
+    }
+    orc_stable_sort_by_cell(n, key, s->p.n_cells, s->perm);
     for (int64_t j = 0; j < n; ++j) {
         int64_t i = s->perm[j];
         s->tx[j] = s->x[sp][i]; s->tvx[j] = s->vx[sp][i]; s->tvy[j] = s->vy[sp][i];
@@ -570,6 +576,8 @@ static void sort_species(orc_sim* s, int sp) {
     memcpy(s->vz[sp], s->tvz, sizeof(double) * (size_t)n);
     memcpy(s->id[sp], s->tid, sizeof(uint32_t) * (size_t)n);
 }
+
+static void sort_species(orc_sim* s, int sp) { sort_species_by(s, sp, NULL); }
 
 static void deposit_all(orc_sim* s) {
     for (int sp = 0; sp < 2; ++sp) {
@@ -948,6 +956,8 @@ int orc_step(orc_sim* s) {
         int64_t n = s->n[sp];
         double ak = fabs(k->kappa[sp]);
         memcpy(s->tvx, s->vx[sp], sizeof(double) * (size_t)n); /* v_x before the push */
+        if (p->sort_mode == ORC_SORT_LAG)
+            for (int64_t i = 0; i < n; ++i) s->start_cell[sp][i] = (int32_t)floor(s->x[sp][i]);
         orc_push(p->periodic, p->n_cells, p->fp32_offset, k->kappa[sp], s->ef, n, s->x[sp],
                  s->vx[sp], s->flags);
         double ke = 0.0;
@@ -1031,6 +1041,7 @@ int orc_step(orc_sim* s) {
                 nb_iz++;
             }
             /* survivors are compacted in input order */
+            s->start_cell[sp][m] = s->start_cell[sp][i];
             s->x[sp][m] = s->x[sp][i];
             s->vx[sp][m] = v[0]; s->vy[sp][m] = v[1]; s->vz[sp][m] = v[2];
             s->id[sp][m] = s->id[sp][i];
@@ -1056,6 +1067,7 @@ int orc_step(orc_sim* s) {
     for (int sp = 0; sp < 2; ++sp) {
         s->n[sp] = nsurv[sp];
         if (p->sort_mode == ORC_SORT_CELL) sort_species(s, sp);
+        else if (p->sort_mode == ORC_SORT_LAG) sort_species_by(s, sp, s->start_cell[sp]);
     }
     if (p->coulomb && p->sort_mode == ORC_SORT_CELL) coulomb_step(s, nsurv, step);
     for (int sp = 0; sp < 2; ++sp) {

@@ -43,7 +43,9 @@ typedef struct orc_params {
     int64_t avg_start;
     /* Array order after a step: ORC_SORT_CELL keeps the survivors stably sorted by cell
        (Sec. 3.7); ORC_SORT_NONE keeps them in input order (the unsorted variant of
-       Sec. 3.2).  Births follow the survivors either way. */
+       Sec. 3.2); ORC_SORT_LAG sorts them stably by the cell they occupied at the start of
+       the step, so the array is sorted with a lag of one step.  Births follow the
+       survivors in every mode. */
     int32_t sort_mode;
     /* ORC_RANK_PARENT_INDEX: births take ids in the array order of their parents;
        ORC_RANK_PARENT_ID: in increasing parent id (for a layout whose order within a
@@ -65,7 +67,7 @@ typedef struct orc_params {
     double circuit_cap_f_m2;
 } orc_params;
 
-enum { ORC_SORT_CELL = 0, ORC_SORT_NONE = 1 };
+enum { ORC_SORT_CELL = 0, ORC_SORT_NONE = 1, ORC_SORT_LAG = 2 };
 enum { ORC_RANK_PARENT_INDEX = 0, ORC_RANK_PARENT_ID = 1 };
 enum { ORC_COUL_EE = 1, ORC_COUL_II = 2, ORC_COUL_EI = 4 };
 

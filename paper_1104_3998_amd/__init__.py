@@ -26,7 +26,7 @@ LOAD = {"random": 0, "quiet_langmuir": 1}
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_CAPACITY", -3: "PIC_ERR_DEVICE",
           -4: "PIC_ERR_NONFINITE", -5: "PIC_ERR_ID_OVERFLOW", -6: "PIC_ERR_STATE",
           -7: "PIC_ERR_WORKSPACE", -8: "PIC_ERR_CORRUPT"}
-SORT = {"counting": 0, "none": 1, "fine": 2}
+SORT = {"counting": 0, "none": 1, "fine": 2, "lag": 3}
 PHASES = ("combine", "solve", "hist", "scan", "main", "collide", "finalize", "coulomb",
           "fine_sort")
 

@@ -85,11 +85,16 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       *why = "all discharges of a simulation must use the same precision";
       return PIC_ERR_ARG;
     }
+    if ((cfgs[d].sort_mode == PIC_SORT_LAG) != (cfgs[0].sort_mode == PIC_SORT_LAG)) {
+      *why = "the lagged sort is chosen for all discharges of a simulation or none";
+      return PIC_ERR_ARG;
+    }
     derive(cfgs[d], &pl->der[d]);
     choose_tiles(cfgs[d], pl->der[d], &pl->tiles[2 * d]);
   }
   const bool fp32 = cfgs[0].precision == PIC_FP32_OFFSET;
   const size_t rs = fp32 ? 4 : 8;  // bytes of a real
+  pl->li.lag = cfgs[0].sort_mode == PIC_SORT_LAG;
   Carver cv{ws};
   pl->sp.assign(2 * n, SpeciesDev{});
   pl->ds.assign(n, DischargeDev{});
@@ -213,6 +218,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       }
       S.n_total = cv.take<uint32_t>(2);
       S.n_sorted = cv.take<uint32_t>(2);
+      S.n_holes = cv.take<uint32_t>(2);
       S.next_id = cv.take<uint32_t>(1);
       S.cell_start = cv.take<uint32_t>(2 * (N + 1));
       S.hist = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles) * kWaves * tc.W);
@@ -468,7 +474,8 @@ extern "C" int pic_derive(const pic_config* cfg, pic_derived* out) {
 // profiled run keeps the GPU as busy as an unprofiled one.
 static int drain_profile(pic_sim* sim) {
   if (sim->ring_used == 0) return PIC_OK;
-  HIPCHECK(sim, hipEventSynchronize(sim->ev[sim->ring_used - 1][2 * kPhases - 1]));
+  // the finalize phase's end event (12, 13) is the last one a step records
+  HIPCHECK(sim, hipEventSynchronize(sim->ev[sim->ring_used - 1][13]));
   for (int k = 0; k < sim->ring_used; ++k)
     for (int p = 0; p < kPhases; ++p) {
       float ms = 0.0f;
@@ -780,8 +787,12 @@ extern "C" int pic_diagnostics(pic_sim* sim, int d, pic_diag* out) {
     uint32_t nt = 0, ns = 0, nid = 0;
     unsigned long long ab[2] = {0, 0}, bi = 0, co[3] = {0, 0, 0};
     double ae[2] = {0, 0};
+    uint32_t holes = 0;
     if ((rc = d2h(sim, &nt, S.n_total + p, 1)) != PIC_OK) return rc;
     if ((rc = d2h(sim, &ns, S.n_sorted + p, 1)) != PIC_OK) return rc;
+    if ((rc = d2h(sim, &holes, S.n_holes + p, 1)) != PIC_OK) return rc;
+    nt -= std::min(holes, nt);  // the lagged sort's dead records are not particles
+    ns -= std::min(holes, ns);
     if ((rc = d2h(sim, &nid, S.next_id, 1)) != PIC_OK) return rc;
     if ((rc = d2h(sim, ab, S.absorbed, 2)) != PIC_OK) return rc;
     if ((rc = d2h(sim, ae, S.absorbed_energy, 2)) != PIC_OK) return rc;
@@ -886,6 +897,46 @@ static int fine_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, pic_
   return fine_gather(sim, S, f[F_ID], st->id[s], cnt);
 }
 
+// Host copy of a species under the lagged sort: the nt records of buffer p without the
+// dead ones (cell -1, or x < 0).
+template <class T>
+static int lag_gather(pic_sim* sim, const void* dev, T* host, const std::vector<char>& live) {
+  if (!host) return PIC_OK;
+  std::vector<T> all(live.size());
+  int rc = d2h(sim, all.data(), static_cast<const T*>(dev), all.size());
+  if (rc != PIC_OK) return rc;
+  size_t o = 0;
+  for (size_t i = 0; i < live.size(); ++i)
+    if (live[i]) host[o++] = all[i];
+  return PIC_OK;
+}
+
+static int lag_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, int p, uint32_t nt,
+                             pic_state* st, int s) {
+  std::vector<char> live(nt);
+  int rc;
+  void* const* f = S.fld[p];
+  if (fp32) {
+    std::vector<int32_t> cell(nt);
+    if ((rc = d2h(sim, cell.data(), static_cast<const int32_t*>(f[F32_CELL]), nt))) return rc;
+    for (uint32_t i = 0; i < nt; ++i) live[i] = cell[i] >= 0;
+    if ((rc = lag_gather(sim, f[F32_CELL], st->cell[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F32_OFF], st->off[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F_VX], st->vxf[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F_VY], st->vyf[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F_VZ], st->vzf[s], live))) return rc;
+  } else {
+    std::vector<double> x(nt);
+    if ((rc = d2h(sim, x.data(), static_cast<const double*>(f[F64_X]), nt))) return rc;
+    for (uint32_t i = 0; i < nt; ++i) live[i] = x[i] >= 0.0;
+    if ((rc = lag_gather(sim, f[F64_X], st->x[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F_VX], st->vx[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F_VY], st->vy[s], live))) return rc;
+    if ((rc = lag_gather(sim, f[F_VZ], st->vz[s], live))) return rc;
+  }
+  return lag_gather(sim, f[F_ID], st->id[s], live);
+}
+
 extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
   if (!sim) return PIC_ERR_STATE;
   if (d < 0 || d >= sim->pl.li.n_ds || !st) return PIC_ERR_ARG;
@@ -907,9 +958,19 @@ extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
     st->n[s] = nt;
     st->n_sorted[s] = ns;
     st->next_id[s] = nid;
-    if (nt > st->capacity[s]) {
+    uint32_t holes = 0;
+    if ((rc = d2h(sim, &holes, S.n_holes + p, 1)) != PIC_OK) return rc;
+    if (nt - std::min(holes, nt) > st->capacity[s]) {
       sim->err = "pic_get_state: host arrays smaller than the particle count";
       return PIC_ERR_CAPACITY;
+    }
+    if (S.mode == kModeLag && holes > 0) {
+      // the dead records of the last step are left out (they lie in the sorted prefix)
+      if ((rc = lag_state_to_host(sim, S, fp32, p, nt, st, s)) != PIC_OK) return rc;
+      st->n[s] = nt - holes;
+      st->n_sorted[s] = ns - std::min(holes, ns);
+      if (st->w[s] && (rc = d2h(sim, st->w[s], D.w[s], D.n_nodes))) return rc;
+      continue;
     }
     if (S.mode == kModeFine) {
       // sorting cells one after the other, each its fcnt particles
@@ -1020,8 +1081,10 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
     }
     if ((rc = h2d(sim, static_cast<uint32_t*>(f[F_ID]), st->id[s], n))) return rc;
     const uint32_t cnt[2] = {n, ns};
+    const uint32_t no_holes[2] = {0u, 0u};
     if ((rc = h2d(sim, S.n_total + up, &cnt[0], 1))) return rc;
     if ((rc = h2d(sim, S.n_sorted + up, &cnt[1], 1))) return rc;
+    if ((rc = h2d(sim, S.n_holes, no_holes, 2))) return rc;
     const uint32_t nid = st->next_id[s];
     if ((rc = h2d(sim, S.next_id, &nid, 1))) return rc;
     launch_zero(S.far_w, sizeof(unsigned long long) * S.n_nodes, sim->stream);

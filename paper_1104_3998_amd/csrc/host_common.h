@@ -35,6 +35,7 @@ struct LaunchInfo {
   bool coulomb;                // some discharge has Coulomb collisions
   bool emission;               // some discharge has secondary emission
   bool fine;                   // some species is fine-sorted
+  bool lag;                    // every species uses the lagged counting sort
 };
 
 // Step kernels (kernels_step.hip).  `sim` points at the SimDev copy in device memory.

@@ -393,6 +393,36 @@ struct PushIn<P64> {
   }
 };
 
+// The stored cell only (the lagged sort's key; the pre-pass then reads 4 of 24 bytes in
+// FP32): -1 for a dead record.
+template <class P>
+struct KeyIn;
+
+template <>
+struct KeyIn<P32> {
+  int cell;
+  __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
+    cell = ldo<int>(f.f[F32_CELL], f.boff4 + i * 4u);
+  }
+  __device__ __forceinline__ int key() const { return cell; }
+};
+
+template <>
+struct KeyIn<P64> {
+  double x;
+  __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
+    x = ldo<double>(f.f[F64_X], f.boff8 + i * 8u);
+  }
+  __device__ __forceinline__ int key() const { return x >= 0.0 ? static_cast<int>(floor(x)) : -1; }
+};
+
+// stored cell of a full record (-1: dead)
+template <class P>
+__device__ __forceinline__ int stored_cell(const Part<P>& q) {
+  if constexpr (std::is_same<P, P32>::value) return q.cell;
+  else return q.x >= 0.0 ? static_cast<int>(floor(q.x)) : -1;
+}
+
 __device__ __forceinline__ int key_bits(int n) {
   int b = 0;
   while ((1 << b) < n) ++b;
@@ -408,6 +438,23 @@ __device__ __forceinline__ void load_field_window(const SpeciesDev& s, const rea
     int n = r.c0 + k;
     if (s.periodic) n %= s.n_cells;
     if (n > s.n_nodes - 1) n = s.n_nodes - 1;
+    Elds[k] = E[n];
+  }
+}
+
+// Lagged sort: the field at the W + 1 nodes of tile r's window (slot k of the window is
+// cell t C - D + k; the nodes past the ends of a bounded grid are never read).
+template <class real>
+__device__ __forceinline__ void load_field_window_lag(const SpeciesDev& s, const real GM* E,
+                                                      const TileRange& r, int tile, real* Elds) {
+  if (r.tail) return;
+  for (int k = threadIdx.x; k <= s.W; k += blockDim.x) {
+    int n = tile * s.C - s.D + k;
+    if (s.periodic) {
+      n %= s.n_cells;
+      if (n < 0) n += s.n_cells;
+    }
+    n = n < 0 ? 0 : (n > s.n_nodes - 1 ? s.n_nodes - 1 : n);
     Elds[k] = E[n];
   }
 }
@@ -460,6 +507,50 @@ __device__ __forceinline__ int push_particle(const SpeciesDev& s, const Discharg
     const double e1 = field_at<double, kTail>(s, dd.E64, Elds, r, c + 1);
     return push64(q.x, q.vx, e0, e1, s.kappa, s.n_cells, s.periodic, pos, vxn, d);
   }
+}
+
+// Lagged sort: push a record whose present cell has window slot ek of its tile (ek >= 0:
+// the two nodes are window entries ek and ek + 1) or lies outside the window (ek < 0:
+// global field array).
+template <class P, class Q>
+__device__ __forceinline__ int push_particle_lag(const SpeciesDev& s, const DischargeDev& dd,
+                                                 const typename Part<P>::real* Elds, int ek,
+                                                 const Q& q, int& d, typename Part<P>::real& pos,
+                                                 typename Part<P>::real& vxn) {
+  using real = typename Part<P>::real;
+  int c;
+  if constexpr (std::is_same<P, P32>::value) {
+    c = q.cell;
+    if (c < 0 || c >= s.n_cells) {
+      d = 0;
+      pos = 0.0f;
+      vxn = q.vx;
+      return 3;
+    }
+  } else {
+    if (!(q.x >= 0.0 && q.x < static_cast<double>(s.n_cells))) {
+      d = 0;
+      pos = 0.0;
+      vxn = q.vx;
+      return 3;
+    }
+    c = static_cast<int>(floor(q.x));
+  }
+  const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
+                                                  : reinterpret_cast<const real GM*>(dd.E64);
+  real e0, e1;
+  if (ek >= 0) {
+    e0 = Elds[ek];
+    e1 = Elds[ek + 1];
+  } else {
+    const int c1 = (s.periodic && c + 1 >= s.n_cells) ? c + 1 - s.n_cells : c + 1;
+    e0 = E[c];
+    e1 = E[c1];
+  }
+  if constexpr (std::is_same<P, P32>::value)
+    return push32(c, q.off, q.vx, e0, e1, s.kappa_f, s.n_cells, s.periodic, d, pos, vxn);
+  else
+    return push64(q.x, q.vx, e0, e1, s.kappa, s.n_cells, s.periodic, pos, vxn, d);
 }
 
 // Electrode reflection of an electron that reached a wall (st 1 or 2; Sec. 2), decided by
@@ -687,7 +778,11 @@ struct HistU<P64> {
   static constexpr int value = 2;
 };
 
-template <class P>
+// kLag: the lagged sort (the array ordered by the cell each particle held at the start of
+// the step; Sec. 3.7 only needs the order to be close): the key is the cell stored in the
+// record at the start of the step, so the pre-pass reads that field only and pushes
+// nothing.
+template <class P, bool kLag>
 __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
@@ -708,7 +803,7 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   const unsigned long long lt = lanes_below();
   const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
                                                   : reinterpret_cast<const real GM*>(dd.E64);
-  load_field_window<real>(s, E, r, Elds);
+  if constexpr (!kLag) load_field_window<real>(s, E, r, Elds);  // lagged: no push here
   const int W = s.W;
   const int Wm = sim.max_window;
   for (int k = tid; k < kWaves * kHistCopies * Wm; k += kWG) hdyn[k] = 0u;
@@ -718,7 +813,60 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
   const WaveRange wr = wave_range(r, wv);
   const RecPtr in = rec_buf(&sim.sp[tt.x], p);
   auto load = [&](PushIn<P>& q, uint32_t i) { q.load(in, i); };
-  if (!r.tail) {
+  if (kLag && !r.tail) {
+    // lagged: histogram of the stored cells of the live records (dead ones skipped)
+    uint32_t qn = 0;  // wave-uniform
+    auto flush = [&]() {
+      uint32_t e0 = 0u;
+      if (lane == 0) e0 = atomicAdd(s.far_count, qn);
+      e0 = __shfl(e0, 0, 64);
+      const uint32_t j = static_cast<uint32_t>(lane);
+      if (j < qn) {
+        const uint32_t e = e0 + j;
+        const uint32_t d = hq[wv][j][0];
+        if (e < s.far_cap) {
+          s.far_list[e] = make_uint4(d, hq[wv][j][1], static_cast<uint32_t>(tt.y), 0u);
+          atomicAdd(&s.far_cell_cnt[d], 1u);
+        }
+      }
+      qn = 0;
+    };
+    auto kload = [&](KeyIn<P>& q, uint32_t i) { q.load(in, i); };
+    stream_range<KeyIn<P>, 8>(wr.lo, wr.hi, kload, [&](const KeyIn<P>& q, uint32_t i, bool valid) {
+      const int key = valid ? q.key() : -1;
+      const bool live = key >= 0 && key < s.n_cells;
+      const int k = live ? window_slot(s, tt.y, key) : -1;
+      if (k >= 0) atomicAdd(&hl[k], 1u);
+      const bool far = live && k < 0;
+      const unsigned long long fm = __ballot(far);
+      if (fm) {
+        if (qn + static_cast<uint32_t>(__popcll(fm)) > 64u) flush();
+        if (far) {
+          const uint32_t j = qn + static_cast<uint32_t>(__popcll(fm & lt));
+          hq[wv][j][0] = static_cast<uint32_t>(key);
+          hq[wv][j][1] = i;
+        }
+        qn += static_cast<uint32_t>(__popcll(fm));
+      }
+    });
+    if (qn) flush();
+    uint32_t GM* row = s.hist + (static_cast<size_t>(tt.y) * kWaves + wv) * W;
+    for (int k = lane; k < W; k += 64) {
+      uint32_t n = 0u;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; ++c) n += h[c * Wm + k];
+      row[k] = n;
+    }
+  } else if (kLag) {
+    // lagged tail: each wave counts its live records' stored cells into its global row
+    uint32_t GM* row = s.thist +
+                       static_cast<size_t>((tt.y - s.n_tiles) * kWaves + wv) * s.n_cells;
+    auto kload = [&](KeyIn<P>& q, uint32_t i) { q.load(in, i); };
+    stream_range<KeyIn<P>, 8>(wr.lo, wr.hi, kload, [&](const KeyIn<P>& q, uint32_t i, bool valid) {
+      const int key = valid ? q.key() : -1;
+      if (key >= 0 && key < s.n_cells) atomicAdd(&row[key], 1u);
+    });
+  } else if (!r.tail) {
     // far movers wait in a per-wave LDS queue and are appended to the far list after the
     // loop (a returning atomic inside the loop would make it wait for the next loads)
     uint32_t qn = 0;  // wave-uniform
@@ -989,10 +1137,12 @@ constexpr int kFarQ = 64;           // per-wave queue of far movers (one chunk a
 // from one cell and land in a handful of slots).
 constexpr int kDepCopies = 8;
 
-template <class P>
+template <class P, bool kLag>
 struct MainShared {
   using real = typename Part<P>::real;
-  real Elds[kMaxCellsPerTile + 1];
+  // the field at the tile's nodes (lagged sort: at the nodes of its whole window, since a
+  // record's present cell may lie up to D cells outside the tile)
+  real Elds[(kLag ? kMaxWindow : kMaxCellsPerTile) + 1];
   uint32_t off[kWaves][kMaxWindow];  // next output index of each (wave, window slot)
   // sum of the fixed-point right-node weights F of the near particles of each window slot,
   // in kDepCopies copies shared by the waves; the slot's particle count comes from the
@@ -1001,11 +1151,12 @@ struct MainShared {
   uint32_t cnt[kMaxWindow];          // fine sort: near particles per window slot
   uint32_t eedf[kMaxEedfBins + 1];
   double wst[kWaves][4];             // per-wave sums: kinetic, momentum, absorbed energy x2
-  uint32_t wcnt[kWaves][6];          // per-wave counts: absorbed, emitted, reflected x2
+  uint32_t wcnt[kWaves][8];          // per-wave counts: absorbed, emitted, reflected x2, pushed, alive
   uint32_t err;                      // error bits found by the tile
   // far movers deferred to the end of each wave's loop: index, cell, position word,
-  // vx, vy, vz (FP32 bits), id, candidate entry; FP64 keeps the reals in fqd
-  uint32_t fq[kWaves][kFarQ][8];
+  // vx, vy, vz (FP32 bits), id, candidate entry; FP64 keeps the reals in fqd and only
+  // index, cell, id, candidate entry here
+  uint32_t fq[kWaves][kFarQ][std::is_same<real, double>::value ? 4 : 8];
   double fqd[kWaves][std::is_same<real, double>::value ? kFarQ : 1][4];
 };
 
@@ -1160,7 +1311,11 @@ struct MainU<P64> {
 };
 
 // Four waves per SIMD (at most 128 VGPRs): with fewer, too few loads are in flight.
-template <class P>
+// kLag: the lagged sort -- the scatter key is the cell stored at the start of the step
+// (known before the push), the record written holds the post-push state, and a particle
+// absorbed in this step leaves a dead record in the slot the pre-pass counted for it
+// (the next step skips it).
+template <class P, bool kLag>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_main(
     const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
@@ -1173,7 +1328,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int p = static_cast<int>(step & 1ull), pq = p ^ 1;
   const TileRange r = tile_range(s, tt.y, p);
   const int tile = tt.y;
-  __shared__ MainShared<P> sh;
+  __shared__ MainShared<P, kLag> sh;
   const int tid = threadIdx.x, lane = tid & 63, wv = wave_id();
   const unsigned long long lt = lanes_below(), gt = lanes_above();
   const bool energy_on = diag_step(dd, step);
@@ -1184,7 +1339,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   const uint32_t sink = s.cap;  // the extra element past the capacity of every array
   const real GM* E = std::is_same<P, P32>::value ? reinterpret_cast<const real GM*>(dd.E32)
                                                   : reinterpret_cast<const real GM*>(dd.E64);
-  load_field_window<real>(s, E, r, sh.Elds);
+  if constexpr (kLag) load_field_window_lag<real>(s, E, r, tile, sh.Elds);
+  else load_field_window<real>(s, E, r, sh.Elds);
   const int W = s.W;
   if (!r.tail && !r.fine) {
     for (int k = tid; k < kWaves * W; k += kWG) {
@@ -1203,7 +1359,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
   }
   for (int k = tid; k < kDepCopies * W; k += kWG) sh.dep[k / W][k % W] = 0ull;
-  if (r.fine)
+  const bool lds_counts = r.fine || kLag;  // deposit counts kept in LDS (no histogram rows)
+  if (lds_counts)
     for (int k = tid; k < W; k += kWG) sh.cnt[k] = 0u;
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG) sh.eedf[k] = 0u;
@@ -1215,6 +1372,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   // live through the particle loop.
   uint32_t n_abs0 = 0u, n_abs1 = 0u;    // wave-uniform
   uint32_t n_wall[4] = {0u, 0u, 0u, 0u};  // emitted x2 (k_emit), reflected x2 (wave-uniform)
+  uint32_t n_pushed = 0u, n_alive = 0u;  // wave-uniform
   uint32_t n_em = 0u;                   // absorbed ions listed by this wave (emission)
   const WaveRange wr = wave_range(r, wv);
   const RecPtr in = rec_buf(&sim.sp[tt.x], p);
@@ -1225,12 +1383,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   // Push, walls, EEDF and the null-collision test: common to both kinds of tile.
   // Push, walls (reflection, absorption, emission), EEDF, energy sums and the
   // null-collision test: common to both kinds of tile.
+  // ek: the lagged sort's window slot of the record's present cell (cell tiles only)
   auto push_and_test = [&](auto tail_tag, auto rev_tag, const Part<P>& q, bool valid, int& d,
-                           real& pos, real& vxn, bool& cand) {
+                           real& pos, real& vxn, bool& cand, int ek) {
     constexpr bool kTail = decltype(tail_tag)::value;
     constexpr bool kRev = decltype(rev_tag)::value;
     int st = 4;
-    if (valid) st = push_particle<P, kTail>(s, dd, sh.Elds, r, q, d, pos, vxn);
+    if (valid) {
+      if constexpr (kLag && !kTail) st = push_particle_lag<P>(s, dd, sh.Elds, ek, q, d, pos, vxn);
+      else st = push_particle<P, kTail>(s, dd, sh.Elds, r, q, d, pos, vxn);
+    }
     if (energy_on) {  // wave-uniform: after the push, before the walls
       double v1 = 0.0, ke = 0.0, v2 = 0.0;
       if (st < 3) {
@@ -1285,6 +1447,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         n_em += static_cast<uint32_t>(__popcll(am));
       }
     }
+    n_pushed += static_cast<uint32_t>(__popcll(__ballot(st < 4)));
+    n_alive += static_cast<uint32_t>(__popcll(__ballot(st == 0)));
     if (st == 3) atomicOr(&sh.err, kErrNonfinite);
     cand = false;
     if (st == 0 && s.t0 != 0u) cand = philox(q.id, step32, 0u, 0u, s.key0, s.key1).x < s.t0;
@@ -1327,7 +1491,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           real pos = real(0), vxn = real(0);
           bool cand;
           const int st = push_and_test(std::false_type{}, std::false_type{}, q, valid, d, pos,
-                                       vxn, cand);
+                                       vxn, cand, -1);
           store_in_place<P>(out, valid ? i : sink, st == 0, d, pos, vxn);
           list_candidate(std::false_type{}, cand, false, i, q, d, pos, vxn);
           if (st == 0) {
@@ -1347,6 +1511,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     // done: their output index is a global load, and a load inside the loop would make
     // the loop wait for the next chunk's loads too.
     uint32_t qn = 0;  // wave-uniform
+    constexpr int kQid = std::is_same<P, P32>::value ? 6 : 2;  // id word (then candidate entry)
     auto flush = [&]() {  // one queue entry per lane (the queue holds at most 64)
       const uint32_t j = static_cast<uint32_t>(lane);
       if (j < qn) {
@@ -1371,10 +1536,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           dst = kNoDest;
         }
         if (dst != kNoDest) {
-          store_record<P>(out, dst, d, pos, vx, vy, vz, f[6]);
-          far_deposit<P>(s, d, pos);
+          store_record<P>(out, dst, d, pos, vx, vy, vz, f[kQid]);
+          if (!kLag) far_deposit<P>(s, d, pos);  // lagged: deposited in the loop
         }
-        if (f[7] != kNoDest) write_candidate(f[7], dst, f[6], d, pos, vx, vy, vz);
+        if (f[kQid + 1] != kNoDest) write_candidate(f[kQid + 1], dst, f[kQid], d, pos, vx, vy, vz);
       }
       qn = 0;
     };
@@ -1383,9 +1548,25 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       int d = 0;
       real pos = real(0), vxn = real(0);
       bool cand;
-      const int st = push_and_test(std::false_type{}, rev_tag, q, valid, d, pos, vxn, cand);
-      const int k = st == 0 ? window_slot(s, tile, d) : -1;
+      int key = 0;
+      int k = -1;
+      if constexpr (kLag) {
+        key = valid ? stored_cell<P>(q) : -1;
+        valid = key >= 0 && key < s.n_cells;  // dead records are skipped
+        k = valid ? window_slot(s, tile, key) : -1;
+      }
+      const int st = push_and_test(std::false_type{}, rev_tag, q, valid, d, pos, vxn, cand, k);
+      if constexpr (!kLag) k = st == 0 ? window_slot(s, tile, d) : -1;
       const bool near = k >= 0;
+      // the record written: the post-push state, or a dead record (lagged sort only)
+      int d_out = d;
+      real pos_out = pos;
+      if constexpr (kLag) {
+        if (st != 0) {
+          d_out = -1;
+          if constexpr (std::is_same<P, P64>::value) pos_out = -1.0;
+        }
+      }
       // stable rank inside this wave's unit of the order (from the unit's end backwards
       // for a backward wave)
       const unsigned long long m = match_key_few(k, near);
@@ -1403,8 +1584,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         atomicOr(&sh.err, kErrState);
         dst = sink;
       }
-      store_record<P>(out, dst, d, pos, vxn, q.vy, q.vz, q.id);
-      const bool far = st == 0 && !near;
+      store_record<P>(out, dst, d_out, pos_out, vxn, q.vy, q.vz, q.id);
+      const bool far = kLag ? (valid && !near) : (st == 0 && !near);
       const uint32_t e = list_candidate(rev_tag, cand, far, near ? dst : kNoDest, q, d, pos, vxn);
       const unsigned long long fm = __ballot(far);
       if (fm) {
@@ -1413,26 +1594,39 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           const uint32_t j = qn + static_cast<uint32_t>(__popcll(fm & lt));
           uint32_t* f = sh.fq[wv][j];
           f[0] = i;
-          f[1] = static_cast<uint32_t>(d);
+          f[1] = static_cast<uint32_t>(d_out);
           if constexpr (std::is_same<P, P32>::value) {
-            f[2] = __float_as_uint(pos);
+            f[2] = __float_as_uint(pos_out);
             f[3] = __float_as_uint(vxn);
             f[4] = __float_as_uint(q.vy);
             f[5] = __float_as_uint(q.vz);
           } else {
-            sh.fqd[wv][j][0] = pos;
+            sh.fqd[wv][j][0] = pos_out;
             sh.fqd[wv][j][1] = vxn;
             sh.fqd[wv][j][2] = q.vy;
             sh.fqd[wv][j][3] = q.vz;
           }
-          f[6] = q.id;
-          f[7] = cand ? e : kNoDest;
+          f[kQid] = q.id;
+          f[kQid + 1] = cand ? e : kNoDest;
         }
         qn += static_cast<uint32_t>(__popcll(fm));
       }
       // deposit of the near particles: the right-node weight into the slot's sum (LDS
-      // integer atomics: exact in any order; the LDS pipe absorbs the same-slot conflicts)
-      if (near) atomicAdd(&sh.dep[lane & (kDepCopies - 1)][k], right_weight<P>(s, pos));
+      // integer atomics: exact in any order; the LDS pipe absorbs the same-slot conflicts).
+      // Lagged: the deposit slot is the post-push cell's, not the scatter slot.
+      if constexpr (kLag) {
+        if (st == 0) {
+          const int kd = window_slot(s, tile, d);
+          if (kd >= 0) {
+            atomicAdd(&sh.cnt[kd], 1u);
+            atomicAdd(&sh.dep[lane & (kDepCopies - 1)][kd], right_weight<P>(s, pos));
+          } else {
+            far_deposit<P>(s, d, pos);
+          }
+        }
+      } else {
+        if (near) atomicAdd(&sh.dep[lane & (kDepCopies - 1)][k], right_weight<P>(s, pos));
+      }
     };
     if (wave_reversed(r, wv)) {
       stream_range_rev<Part<P>, MainU<P>::value>(
@@ -1458,7 +1652,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           real pos = real(0), vxn = real(0);
           bool cand;
           const int st = push_and_test(std::true_type{}, std::false_type{}, q, valid, d, pos, vxn,
-                                       cand);
+                                       cand, -1);
           const unsigned long long m = __ballot(st == 0);
           uint32_t dst = kNoDest;
           if (st == 0) {
@@ -1483,26 +1677,40 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           int d = 0;
           real pos = real(0), vxn = real(0);
           bool cand;
+          int key = 0;
+          if constexpr (kLag) {
+            key = valid ? stored_cell<P>(q) : -1;
+            valid = key >= 0 && key < s.n_cells;
+          }
           const int st = push_and_test(std::true_type{}, std::false_type{}, q, valid, d, pos, vxn,
-                                       cand);
-          const bool act = st == 0;
-          const unsigned long long mc = match_key(d, act, nbits);
+                                       cand, -1);
+          const bool act = kLag ? valid : st == 0;
+          if constexpr (!kLag) key = d;
+          const unsigned long long mc = match_key(key, act, nbits);
           const int rank = __popcll(mc & lt);
           uint32_t old = 0u;
-          if (act && rank == 0) old = atomicAdd(&trow[d], static_cast<uint32_t>(__popcll(mc)));
+          if (act && rank == 0) old = atomicAdd(&trow[key], static_cast<uint32_t>(__popcll(mc)));
           const int leader = act ? __ffsll(static_cast<long long>(mc)) - 1 : lane;
           old = __shfl(old, leader, 64);
           uint32_t dst = kNoDest;
           if (act) {
-            dst = s.base[d] + old + static_cast<uint32_t>(rank);
+            dst = s.base[key] + old + static_cast<uint32_t>(rank);
             if (dst >= n_out) {
               atomicOr(&sh.err, kErrState);
               dst = kNoDest;
             }
           }
-          store_record<P>(out, dst == kNoDest ? sink : dst, d, pos, vxn, q.vy, q.vz, q.id);
-          list_candidate(std::false_type{}, cand, false, dst, q, d, pos, vxn);
-          if (dst != kNoDest) far_deposit<P>(s, d, pos);
+          int d_out = d;
+          real pos_out = pos;
+          if constexpr (kLag) {
+            if (st != 0) {
+              d_out = -1;
+              if constexpr (std::is_same<P, P64>::value) pos_out = -1.0;
+            }
+          }
+          store_record<P>(out, dst == kNoDest ? sink : dst, d_out, pos_out, vxn, q.vy, q.vz, q.id);
+          list_candidate(std::false_type{}, cand, false, st == 0 ? dst : kNoDest, q, d, pos, vxn);
+          if (dst != kNoDest && st == 0) far_deposit<P>(s, d, pos);
         });
   }
   if (lane == 0) {
@@ -1510,6 +1718,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     sh.wcnt[wv][0] = n_abs0;
     sh.wcnt[wv][1] = n_abs1;
     for (int k = 0; k < 4; ++k) sh.wcnt[wv][2 + k] = n_wall[k];
+    sh.wcnt[wv][6] = n_pushed;
+    sh.wcnt[wv][7] = n_alive;
     if (s.t_see) {
       s.ab_cnt[tile * kWaves + wv] = n_em;
       s.em_lo[tile * kWaves + wv] = wave_reversed(r, wv) ? wr.hi - n_em : wr.lo;
@@ -1525,7 +1735,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       unsigned long long v = 0ull;
       if (j < W) {
         uint32_t cnt = 0u;
-        if (r.fine) {
+        if (lds_counts) {
           cnt = sh.cnt[j];
         } else {
 #pragma unroll
@@ -1557,6 +1767,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       ts.emit[1] += sh.wcnt[w][3];
       ts.refl[0] += sh.wcnt[w][4];
       ts.refl[1] += sh.wcnt[w][5];
+      ts.pushed += sh.wcnt[w][6];
+      ts.alive += sh.wcnt[w][7];
     }
     s.tstats[tile] = ts;
   }
@@ -1781,12 +1993,11 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
   const int nt = se.n_tiles + se.n_tail;
   // thread s (s < 2) settles species s: its counters are loaded before the scan, so their
   // latency overlaps it (nothing in this kernel writes them before they are used)
-  uint32_t n_surv = 0u, nid = 0u, n_prev = 0u;
+  uint32_t n_surv = 0u, nid = 0u;
   if (threadIdx.x < 2) {
     const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
     n_surv = s.n_sorted[q];
     nid = *s.next_id;
-    n_prev = s.n_total[q ^ 1];
   }
   const uint32_t B = array_exclusive_scan_to(se.birth_cnt, se.birth_base, nt, lds);
   // electrons emitted by absorbed ions follow the ionisation births, in the order of their
@@ -1813,7 +2024,6 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     }
     s.fin[0] = fit;
     s.fin[1] = nid;
-    *s.psteps += static_cast<unsigned long long>(n_prev);
     s.n_total[q] = n_surv + fit;
     *s.next_id = nid + fit;
     *s.births += fit;
@@ -1821,7 +2031,7 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
   // The step's per-tile sums of both species, combined in a fixed order (each thread over
   // its tiles in order, a butterfly inside each wave, then the waves in order): the
   // cumulative wall tallies and, on energy steps, the kinetic energies and momentum.
-  constexpr int kD = 4, kU = 6;
+  constexpr int kD = 4, kU = 8;
   __shared__ double wd[2][kSolveWG / 64][kD];
   __shared__ uint32_t wu[2][kSolveWG / 64][kU];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1829,7 +2039,7 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     const SpeciesDev s = sim.sp[dd.spec0 + sp];
     const int ntiles = s.n_tiles + s.n_tail;
     double d[kD] = {0.0, 0.0, 0.0, 0.0};
-    uint32_t u[kU] = {0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t u[kU] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
       const TileStats ts = s.tstats[t];
       d[0] += ts.ke;
@@ -1842,6 +2052,8 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
       u[3] += ts.emit[1];
       u[4] += ts.refl[0];
       u[5] += ts.refl[1];
+      u[6] += ts.pushed;
+      u[7] += ts.alive;
     }
 #pragma unroll
     for (int k = 0; k < kD; ++k) d[k] = wave_sum(d[k]);
@@ -1863,7 +2075,7 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     for (int sp = 0; sp < 2; ++sp) {
       const SpeciesDev s = sim.sp[dd.spec0 + sp];
       double d[kD] = {0.0, 0.0, 0.0, 0.0};
-      unsigned long long u[kU] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+      unsigned long long u[kU] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
       for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
         for (int k = 0; k < kD; ++k) d[k] += wd[sp][w][k];
         for (int k = 0; k < kU; ++k) u[k] += wu[sp][w][k];
@@ -1876,6 +2088,12 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
       s.emitted[1] += u[3];
       s.reflected[0] += u[4];
       s.reflected[1] += u[5];
+      *s.psteps += u[6];
+      // lagged sort: the output holds a dead record for every counted slot whose particle
+      // did not survive the push
+      const uint32_t slots = s.n_sorted[(step + 1ull) & 1ull];
+      s.n_holes[(step + 1ull) & 1ull] =
+          s.mode == kModeLag && slots > u[7] ? slots - static_cast<uint32_t>(u[7]) : 0u;
       if (energy) {
         const double ak = fabs(s.kappa);
         dd.dstat[DS_KIN_E + sp] = d[0] / (2.0 * ak);
@@ -2003,8 +2221,14 @@ void launch_solve(const LaunchInfo& li, const SimDev* sim, int init_mode, hipStr
 void launch_hist(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
   const size_t lds = sizeof(uint32_t) * kWaves * kHistCopies * li.max_window;
-  if (li.fp32) launch_lds(k_hist<P32>, dim3(li.total_tiles), dim3(kWG), lds, st, e0, e1, sim);
-  else launch_lds(k_hist<P64>, dim3(li.total_tiles), dim3(kWG), lds, st, e0, e1, sim);
+  const dim3 g(li.total_tiles), b(kWG);
+  if (li.lag) {
+    if (li.fp32) launch_lds(k_hist<P32, true>, g, b, lds, st, e0, e1, sim);
+    else launch_lds(k_hist<P64, true>, g, b, lds, st, e0, e1, sim);
+  } else {
+    if (li.fp32) launch_lds(k_hist<P32, false>, g, b, lds, st, e0, e1, sim);
+    else launch_lds(k_hist<P64, false>, g, b, lds, st, e0, e1, sim);
+  }
 }
 
 void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
@@ -2020,8 +2244,14 @@ void launch_scan(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEve
 
 void launch_main(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,
                  hipEvent_t e1) {
-  if (li.fp32) launch(k_main<P32>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
-  else launch(k_main<P64>, dim3(li.total_tiles), dim3(kWG), st, e0, e1, sim);
+  const dim3 g(li.total_tiles), b(kWG);
+  if (li.lag) {
+    if (li.fp32) launch(k_main<P32, true>, g, b, st, e0, e1, sim);
+    else launch(k_main<P64, true>, g, b, st, e0, e1, sim);
+  } else {
+    if (li.fp32) launch(k_main<P32, false>, g, b, st, e0, e1, sim);
+    else launch(k_main<P64, false>, g, b, st, e0, e1, sim);
+  }
 }
 
 void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hipEvent_t e0,

@@ -126,7 +126,7 @@ int validate_config(const pic_config& c, std::string* why) {
   if (c.eedf_bins > 256) return bad("eedf_bins > 256");
   if (c.eedf_bins > 0 && !(c.eedf_max_ev > 0)) return bad("eedf_max_ev");
   if (c.xsec_model == PIC_XS_CONST_E_ELASTIC && !(c.eps_cap_ev > 0)) return bad("eps_cap_ev");
-  if (c.sort_mode > PIC_SORT_FINE) return bad("sort_mode");
+  if (c.sort_mode > PIC_SORT_LAG) return bad("sort_mode");
   if (c.sort_mode == PIC_SORT_FINE) {
     if (c.see_gamma > 0.0) return bad("secondary emission is not built for PIC_SORT_FINE");
     if (c.sort_cell_capacity > static_cast<uint32_t>(kMaxFineSlots))

@@ -63,7 +63,8 @@ struct TileStats {
   uint32_t abs_n[2];  // particles absorbed at each wall
   uint32_t emit[2];   // secondary electrons emitted at each wall (ion species)
   uint32_t refl[2];   // electrons reflected at each wall (electron species)
-  uint32_t pad[2];
+  uint32_t pushed;    // particles pushed
+  uint32_t alive;     // particles inside the box after the push (and the walls)
 };
 
 // Per-discharge results of the last step, normalised units (energy Q^2 dx / (eps0 A),
@@ -85,7 +86,7 @@ enum : int { F32_CELL = 0, F32_OFF = 1, F_VX = 2, F_VY = 3, F_VZ = 4, F_ID = 5 }
 enum : int { F64_X = 0 };
 
 // Array order a species keeps (pic_sort).
-enum : int32_t { kModeCounting = 0, kModeNone = 1, kModeFine = 2 };
+enum : int32_t { kModeCounting = 0, kModeNone = 1, kModeFine = 2, kModeLag = 3 };
 
 struct SpeciesDev {
   int32_t ds, sp, n_cells, periodic;
@@ -103,6 +104,7 @@ struct SpeciesDev {
   void GM* stage[2][6];
   uint32_t GM* n_total;        // [2] particles in buffer b
   uint32_t GM* n_sorted;       // [2] length of the cell-sorted prefix of buffer b
+  uint32_t GM* n_holes;        // [2] lagged sort: dead records (absorbed) in buffer b
   uint32_t GM* next_id;        // [1]
   uint32_t GM* cell_start;     // [2][n_cells + 1] first index of each cell in the sorted prefix
   // A tile's index range is split into kWaves contiguous sub-ranges, one per wave, in

@@ -198,7 +198,8 @@ def compare_fine(sim, orc, label, fp32=False, gbase=None, obase=None):
     cell that is not fixed: the state is compared particle by particle through the ids
     (the same set; positions, velocities at the path's bar), the array must run through
     the sorting cells in order, and node weights and tallies must match."""
-    from test_gpu_parity import oracle_tallies, positions, same_tallies, tallies_of, velocities
+    from test_gpu_parity import (oracle_mod_deposit, oracle_tallies, positions, same_tallies,
+                                 tallies_of, velocities)
     st = sim.get_state()
     g, o = tallies_of(sim.diagnostics()), oracle_tallies(orc.tallies())
     G = max(1, int(sim.workloads[0].get("grid_points_per_sort_cell", 3)) - 1)
@@ -221,9 +222,22 @@ def compare_fine(sim, orc, label, fp32=False, gbase=None, obase=None):
             assert np.max(np.abs(x[ig] - xo), initial=0) <= 1e-12 * sim.workloads[0]["n_cells"]
             assert np.max(np.abs(v - vo), initial=0) <= 1e-12 * scale, (label, s, "v")
         wo = orc.grid("w_e" if s == 0 else "w_i")
-        tol = 1e-9 if fp32 else 1e-12
-        assert np.max(np.abs(a["w"] - wo)) <= tol * max(wo.max(), 1.0), (label, s, "w")
-        same_tallies(g[s], o[s], label, s)
+        if fp32:
+            # free-running FP32 positions drift apart by up to 1e-4 cells (above), and the
+            # node weights with them: they must be the oracle's deposit of the GPU's own
+            # particles to 1e-9 and follow the oracle's weights to 1e-4 of max w
+            wl_ = sim.workloads[0]
+            wself = oracle_mod_deposit(wl_["periodic"], wl_["n_cells"], x)
+            assert np.max(np.abs(a["w"] - wself)) <= 1e-9 * max(wself.max(), 1.0), (label, s)
+            assert np.max(np.abs(a["w"] - wo)) <= 1e-4 * max(wo.max(), 1.0), (label, s, "w")
+            # the absorbed energy sums the drifted FP32 velocities: held to their 1e-5 bar
+            for k in ("coll", "absorbed", "births"):
+                assert g[s][k] == o[s][k], (label, s, k)
+            for w in range(2):
+                assert g[s]["abs_e"][w] == pytest.approx(o[s]["abs_e"][w], rel=1e-5), (label, s)
+        else:
+            assert np.max(np.abs(a["w"] - wo)) <= 1e-12 * max(wo.max(), 1.0), (label, s, "w")
+            same_tallies(g[s], o[s], label, s)
 
 
 @pytest.mark.parametrize("G", [1, 2, 4])
@@ -276,3 +290,71 @@ def test_fine_sort_fp32_free_running(fspic, oracle_mod):
         orc.step(1)
         compare_fine(sim, orc, "fine fp32 step %d" % k, fp32=True)
     sim.close()
+
+
+# ------------------------------------------------------------------ the lagged sort
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+def test_lagged_sort_one_step_from_seeded_state(fspic, oracle_mod, precision):
+    """The lagged sort (the array ordered by the cell each particle held at the start of
+    the step; absorbed particles leave dead records): one step from a seeded state with a
+    births tail and fast electrons, in the ionising bounded discharge."""
+    from test_gpu_parity import one_step
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0, sort_mode="lag")
+    st = workloads.synthetic_state(wl["n_cells"], (20000, 20000), precision, seed=53,
+                                   vth=(2.5, 0.3), tail=(300, 300), fast=(200, 0),
+                                   fast_speed=(3.0, 60.0))
+    one_step(fspic, oracle_mod, wl, st, precision, label="lag " + precision)
+
+
+def test_lagged_sort_periodic_one_step(fspic, oracle_mod):
+    """Periodic plasma with far movers across the seam under the lagged sort."""
+    from test_gpu_parity import one_step
+    for precision in ("fp64", "fp32_offset"):
+        wl = workloads.periodic_c1(sort_mode="lag")
+        st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
+                                       seed=59, vth=(0.4, 0.01), fast=(300, 0),
+                                       fast_speed=(3.0, 60.0))
+        one_step(fspic, oracle_mod, wl, st, precision, label="lag periodic " + precision)
+
+
+def test_lagged_sort_free_running_matches_oracle(fspic, oracle_mod):
+    """20 free FP64 steps of the ionising bounded discharge with electron reflection under
+    the lagged sort, each side from its own load: the same array order (dead records left
+    out), states, weights and tallies."""
+    from test_gpu_parity import compare_fp64
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0, sort_mode="lag", refl_e=0.1)
+    sim = fspic.Simulation(wl, "fp64")
+    orc = oracle_mod.Oracle(wl)
+    orc.load()
+    for k in range(20):
+        sim.step(1)
+        orc.step(1)
+        compare_fp64(sim, orc, "lag step %d" % k)
+    assert sum(sim.diagnostics().births) > 0
+    assert sum(sim.diagnostics().absorbed[0]) > 0
+    sim.close()
+
+
+def test_lagged_sort_same_physics_as_counting_sort(fspic):
+    """The array order does not enter the physics: 20 FP64 steps of the same collisionless
+    discharge under the lagged and the counting sort give the same particles (matched by
+    id) bit for bit, the same node weights (the fixed-point deposit does not depend on
+    the order) and the same absorbed counts."""
+    from test_gpu_parity import positions, tallies_of, velocities
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=0.0, xsec="none")
+    sims = {m: fspic.Simulation(dict(wl, sort_mode=m), "fp64") for m in ("counting", "lag")}
+    for sim in sims.values():
+        sim.step(20)
+    a, b = (sims[m].get_state() for m in ("counting", "lag"))
+    for s in (0, 1):
+        assert a[s]["n"] == b[s]["n"]
+        ia, ib = np.argsort(a[s]["id"]), np.argsort(b[s]["id"])
+        assert np.array_equal(a[s]["id"][ia], b[s]["id"][ib])
+        assert np.array_equal(positions(a[s], False)[ia], positions(b[s], False)[ib])
+        assert np.array_equal(velocities(a[s], False)[:, ia], velocities(b[s], False)[:, ib])
+        assert np.array_equal(a[s]["w"], b[s]["w"])
+    ta, tb = (tallies_of(sims[m].diagnostics()) for m in ("counting", "lag"))
+    for s in (0, 1):
+        assert ta[s]["absorbed"] == tb[s]["absorbed"]
+    for sim in sims.values():
+        sim.close()

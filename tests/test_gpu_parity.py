@@ -105,8 +105,10 @@ def same_tallies(g, o, label, s):
             (label, s, "absorbed energy", w, g["abs_e"][w], o["abs_e"][w])
 
 
-def compare_fp64(sim, orc, label, gbase=None, obase=None, d=0):
-    """Exact permutation / counts / tallies, 1e-12 on positions, velocities and weights."""
+def compare_fp64(sim, orc, label, gbase=None, obase=None, d=0, w_tol=1e-12):
+    """Exact permutation / counts / tallies, 1e-12 on positions and velocities, w_tol of
+    max w on the node weights (1e-12 unless a caller states why its weights may follow a
+    position difference inside the 1e-12 * N bar more closely)."""
     st = sim.get_state(d)
     g = tallies_of(sim.diagnostics(d))
     o = oracle_tallies(orc.tallies())
@@ -126,7 +128,7 @@ def compare_fp64(sim, orc, label, gbase=None, obase=None, d=0):
         scale = np.max(np.abs(vo), initial=1e-30)
         assert np.max(np.abs(v - vo), initial=0) <= 1e-12 * scale, (label, s, "v")
         wo = orc.grid("w_e" if s == 0 else "w_i")
-        assert np.max(np.abs(a["w"] - wo)) <= 1e-12 * max(wo.max(), 1.0), (label, s, "w")
+        assert np.max(np.abs(a["w"] - wo)) <= w_tol * max(wo.max(), 1.0), (label, s, "w")
         same_tallies(g[s], o[s], label, s)
     return st
 
@@ -175,8 +177,15 @@ def compare_fp32(sim, orc, st_in, label, gbase=None, obase=None, coll_slack=0, d
         ns = a["n_sorted"]
         surv = a["id"][:ns]
         in_order = inp["id"][np.isin(inp["id"], surv)]
-        if sim.workloads[d].get("sort_mode", "counting") == "none":
+        mode = sim.workloads[d].get("sort_mode", "counting")
+        if mode == "none":
             expect = in_order
+        elif mode == "lag":
+            # lagged: the stable sort of the input order by the cells the input held
+            xin = positions(inp, True)
+            key_of = dict(zip(inp["id"].tolist(), np.floor(xin).astype(np.int64).tolist()))
+            keys = np.array([key_of[i] for i in in_order.tolist()], dtype=np.int64)
+            expect = in_order[np.argsort(keys, kind="stable")]
         else:
             by_id = np.argsort(surv)
             keys = a["cell"][:ns][by_id][np.searchsorted(surv[by_id], in_order)].astype(np.int64)
@@ -368,7 +377,15 @@ def test_series_capacitor_circuit_matches_oracle(fspic, oracle_mod):
     for k in range(20):
         sim.step(1)
         orc.step(1)
-        compare_fp64(sim, orc, "circuit step %d" % k)
+        # the electrode potential follows the conductor charge, a running sum of wall
+        # fluxes and solve residues: positions stay inside the 1e-12 * N bar but drift
+        # apart by up to ~1e-11 cells over 20 free steps, and a node's weight sums that
+        # drift over its particles, so the weights are held to 1e-10 of max w against
+        # the oracle and to 1e-12 against the oracle's deposit of the GPU's own particles
+        st = compare_fp64(sim, orc, "circuit step %d" % k, w_tol=1e-10)
+        for s in (0, 1):
+            wself = oracle_mod_deposit(wl["periodic"], wl["n_cells"], positions(st[s], False))
+            assert np.max(np.abs(st[s]["w"] - wself)) <= 1e-12 * max(wself.max(), 1.0), k
         g, t = sim.diagnostics(), orc.tallies()
         assert g.phi_driven_v / d.phi_scale == pytest.approx(t.phi0, rel=1e-10, abs=1e-10)
         assert g.circuit_charge == pytest.approx(t.q_circuit, rel=1e-10, abs=1e-10)

@@ -238,7 +238,8 @@ def test_tile_geometry_does_not_change_results(fspic, precision):
     """The tile geometry (cells per tile, window) changes speed only: 20 steps of the RF
     discharge with the default geometry and with half-size electron tiles, double-size
     ion tiles and a half window give the same state bit for bit (the fixed-point deposit
-    makes the node weights independent of which windows a particle lands in)."""
+    makes the node weights independent of which windows a particle lands in) and the same
+    integer tallies."""
     wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0)
     from paper_1104_3998_amd import autotune as at
     alt = at.scaled_tuning(at.rule_geometry([wl], precision), 0.5, 2.0, 0.5)
@@ -248,7 +249,14 @@ def test_tile_geometry_does_not_change_results(fspic, precision):
     a.step(20)
     b.step(20)
     bitwise_equal_states(a.get_state(), b.get_state(), precision == "fp32_offset", "tiles")
-    bitwise_equal_diagnostics(a.diagnostics(), b.diagnostics(), "tiles")
+    # the integer tallies are the same; the absorbed energy is an FP64 sum grouped by tile,
+    # so another geometry rounds it differently in the last bits
+    ga, gb = tallies_of(a.diagnostics()), tallies_of(b.diagnostics())
+    for sp in (0, 1):
+        for k in ("coll", "absorbed", "births"):
+            assert ga[sp][k] == gb[sp][k], (sp, k)
+        for w in range(2):
+            assert ga[sp]["abs_e"][w] == pytest.approx(gb[sp]["abs_e"][w], rel=1e-12, abs=1e-12)
     a.close()
     b.close()
 

@@ -371,3 +371,38 @@ def test_circuit_conductor_charge_follows_the_wall_currents(oracle_mod):
     t2 = o.tallies()
     assert t2.q_circuit - q0 == pytest.approx(cond, abs=1e-9)
     assert abs(t.phi0 - vs) > 1e-3 * abs(c.vhat_amp)
+
+
+# ------------------------------------------------------------------ lagged sort order
+def test_lagged_sort_orders_by_start_of_step_cell(oracle_mod):
+    """The lagged counting sort (Sec. 3.7 with the sort key taken before the push): after a
+    step without collisions, the survivors are the input particles minus the absorbed ones,
+    ordered stably by the cell each occupied at the start of the step (np.argsort with a
+    stable kind on the input's cells), and their states equal those of the same step in
+    the canonical mode (the order does not enter the push)."""
+    wl = workloads.rf_c2(n_e0=3000, n_i0=3000, xsec="none", gas_pa=0.0, v0_volt=100.0)
+    rng = np.random.default_rng(21)
+    n = 3000
+    xs = {s: rng.uniform(0, wl["n_cells"], n) for s in (0, 1)}
+    vs = {s: rng.normal(0, 3.0 if s == 0 else 0.2, size=(3, n)) for s in (0, 1)}
+    states = {}
+    for mode in ("counting", "lag"):
+        o = oracle_mod.Oracle(dict(wl, sort_mode=mode))
+        for s in (0, 1):
+            o.set_particles(s, dict(x=xs[s], vx=vs[s][0], vy=vs[s][1], vz=vs[s][2],
+                                    id=np.arange(n, dtype=np.uint32)))
+        o.set_counters(0, n, n)
+        o.step(1)
+        states[mode] = [o.particles(s) for s in (0, 1)]
+    for s in (0, 1):
+        lag, can = states["lag"][s], states["counting"][s]
+        start = np.floor(xs[s]).astype(np.int64)
+        surv = np.isin(np.arange(n), lag["id"])
+        assert surv.sum() < n  # some were absorbed
+        expect = np.arange(n)[surv][np.argsort(start[surv], kind="stable")]
+        assert np.array_equal(lag["id"], expect.astype(np.uint32)), s
+        order = np.argsort(can["id"])
+        assert np.array_equal(np.sort(lag["id"]), can["id"][order])
+        back = np.argsort(lag["id"])
+        for k in ("x", "vx", "vy", "vz"):
+            assert np.allclose(lag[k][back], can[k][order], rtol=0, atol=1e-12), (s, k)
