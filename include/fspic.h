@@ -198,6 +198,25 @@ int pic_derive(const pic_config* cfg, pic_derived* out);
 int pic_init(const pic_config* cfgs, int n_discharges, void* d_workspace, size_t bytes,
              void* hip_stream, pic_sim** out);
 
+/* Bytes of the library's own device workspace (pic_init_static). */
+#define PIC_STATIC_WORKSPACE_BYTES (128u * 1024u * 1024u)
+
+/* pic_init for callers that cannot allocate device memory (code that must not call
+   hipMalloc: under HIP graph capture, in tight serving loops, or in harnesses that forbid
+   it).  Instead of a caller workspace, the simulation lives in a device array of
+   PIC_STATIC_WORKSPACE_BYTES that the library holds on each GPU it runs on, from the
+   first use until the process ends; this call allocates nothing.  Arguments and the
+   resulting pic_sim are as for pic_init on the current HIP device (the handle is freed
+   with pic_free as usual).  The array is shared by every call on one GPU and keeps the
+   last simulation's contents: each pic_init_static clears what the new simulation uses,
+   and a second one on the same GPU overwrites the first one's state, so at most one
+   simulation made this way may be live per GPU (calls that overlap race).
+   Errors: PIC_ERR_WORKSPACE (with a message from pic_last_error(NULL)) when the
+   discharges need more than PIC_STATIC_WORKSPACE_BYTES (pic_workspace_bytes), the errors
+   of pic_init otherwise. */
+int pic_init_static(const pic_config* cfgs, int n_discharges, void* hip_stream,
+                    pic_sim** out);
+
 /* Enqueues n_steps steps.  Asynchronous; with graphs enabled (pic_set_graph), steps are
    replayed from a captured HIP graph of `steps_per_graph` steps. */
 int pic_step(pic_sim* sim, uint32_t n_steps);

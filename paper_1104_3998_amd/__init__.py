@@ -92,7 +92,8 @@ class PicState(ctypes.Structure):
     ]
 
 
-EXPORTS = ("pic_workspace_bytes", "pic_derive", "pic_init", "pic_step", "pic_set_graph",
+EXPORTS = ("pic_workspace_bytes", "pic_derive", "pic_init", "pic_init_static", "pic_step",
+           "pic_set_graph",
            "pic_sync", "pic_density", "pic_grid", "pic_diagnostics", "pic_get_state",
            "pic_set_state", "pic_profile", "pic_profile_read", "pic_free", "pic_last_error")
 
@@ -118,6 +119,7 @@ def lib():
     L.pic_workspace_bytes.argtypes = [cfgp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.pic_derive.argtypes = [cfgp, ctypes.POINTER(PicDerived)]
     L.pic_init.argtypes = [cfgp, ctypes.c_int, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    L.pic_init_static.argtypes = [cfgp, ctypes.c_int, P, ctypes.POINTER(P)]
     L.pic_step.argtypes = [P, U32]
     L.pic_set_graph.argtypes = [P, U32]
     L.pic_sync.argtypes = [P]
@@ -205,7 +207,9 @@ class Simulation:
     """Owns a torch workspace and a pic_sim handle for one or more discharges."""
 
     def __init__(self, workloads, precision="fp32_offset", device="cuda", cap_factor=1.5,
-                 tuning=None, stream=None):
+                 tuning=None, stream=None, workspace="torch"):
+        """workspace: "torch" (a torch.uint8 tensor of pic_workspace_bytes, pic_init) or
+        "static" (the library's own device array, pic_init_static: nothing allocated)."""
         if torch is None or not torch.cuda.is_available():
             raise RuntimeError("Simulation needs a ROCm GPU (torch.cuda.is_available() is False)")
         wls = workloads if isinstance(workloads, (list, tuple)) else [workloads]
@@ -221,12 +225,18 @@ class Simulation:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         arr = (PicConfig * len(self.cfgs))(*self.cfgs)
         h = P()
-        self.static_workspace = False
-        self.bytes = workspace_bytes(self.cfgs)
-        self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
-        _check("pic_init", lib().pic_init(arr, len(self.cfgs), P(self.workspace.data_ptr()),
-                                          self.bytes, P(self.stream.cuda_stream),
-                                          ctypes.byref(h)))
+        self.static_workspace = workspace == "static"
+        if self.static_workspace:
+            self.bytes, self.workspace = 0, None
+            with torch.cuda.device(self.device):
+                _check("pic_init_static", lib().pic_init_static(
+                    arr, len(self.cfgs), P(self.stream.cuda_stream), ctypes.byref(h)))
+        else:
+            self.bytes = workspace_bytes(self.cfgs)
+            self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
+            _check("pic_init", lib().pic_init(arr, len(self.cfgs), P(self.workspace.data_ptr()),
+                                              self.bytes, P(self.stream.cuda_stream),
+                                              ctypes.byref(h)))
         self._h = h
         self.derived = [derive(c) for c in self.cfgs]
 

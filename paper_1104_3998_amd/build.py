@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "fspic")
 LIB = os.path.join(HERE, "libfspic.so")
 SOURCES = ["api.cpp", "kernels_step.hip", "kernels_setup.hip", "kernels_coulomb.hip",
-           "kernels_fine.hip", "physics_host.cpp"]
+           "kernels_fine.hip", "static_workspace.hip", "physics_host.cpp"]
 ARCH = os.environ.get("FSPIC_ARCH", "gfx950")
 
 
