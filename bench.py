@@ -59,6 +59,7 @@ def read_traffic(precision):
 
 
 PROGRESS_STEPS = 0  # --progress N: report every N warm-up steps
+SORT = "lag"        # --sort: the sort of the headline and the gates
 
 
 def _psteps(sim):
@@ -206,7 +207,7 @@ def density_gate(fs, torch, workloads, steps, seeds):
       difference of the averages (systematic error of the FP32 layout) with its standard
       error (what chaos alone leaves in a mean over that many pairs)."""
     import numpy as np
-    wl = workloads.large_c3(avg_start=steps // 2)
+    wl = workloads.large_c3(avg_start=steps // 2, sort_mode=SORT)
     ref = _averages(fs, torch, wl, "fp64", steps)
     f32 = _averages(fs, torch, wl, "fp32_offset", steps, keep_state=True)
     f32b = _averages(fs, torch, wl, "fp32_offset", steps, keep_state=True)
@@ -214,8 +215,8 @@ def density_gate(fs, torch, workloads, steps, seeds):
         np.array_equal(f32["state"][s][f].view(np.uint8), f32b["state"][s][f].view(np.uint8))
         for s in (0, 1) for f in ("cell", "off", "vxf", "vyf", "vzf", "id"))
     del f32["state"], f32b
-    seed1 = _averages(fs, torch, workloads.large_c3(avg_start=steps // 2, seed=1), "fp64",
-                      steps)
+    seed1 = _averages(fs, torch, workloads.large_c3(avg_start=steps // 2, seed=1,
+                                                    sort_mode=SORT), "fp64", steps)
     st64 = _rounded_fp64_state(fs, wl)
     pert = _averages(fs, torch, wl, "fp64", steps, state=st64)
     del st64
@@ -225,7 +226,7 @@ def density_gate(fs, torch, workloads, steps, seeds):
     refs = {k: [] for k in QUANT}
     pairs = []
     for seed in range(100, 100 + seeds):
-        w = workloads.large_c3(avg_start=steps // 2, seed=seed)
+        w = workloads.large_c3(avg_start=steps // 2, seed=seed, sort_mode=SORT)
         a = _norm_eedf(_averages(fs, torch, w, "fp32_offset", steps))
         b = _norm_eedf(_averages(fs, torch, w, "fp64", steps))
         pairs.append(rel_l2(a, b))
@@ -286,11 +287,11 @@ def rf_gate(fs, torch, workloads, steps):
     time averages over the last RF cycle of `steps` steps from the FP64 GPU path against
     the FP64 oracle run on the host from the same seed, with the FP64 seed + 1 run as the
     statistical floor, and the FP32 layout against FP64."""
-    wl = workloads.rf_c2(steps=steps, avg_start=max(0, steps - 400))
+    wl = workloads.rf_c2(steps=steps, avg_start=max(0, steps - 400), sort_mode=SORT)
     g64 = _averages(fs, torch, wl, "fp64", steps)
     g32 = _averages(fs, torch, wl, "fp32_offset", steps)
     seed1 = _averages(fs, torch, workloads.rf_c2(steps=steps, avg_start=max(0, steps - 400),
-                                                 seed=1), "fp64", steps)
+                                                 seed=1, sort_mode=SORT), "fp64", steps)
     t0 = time.perf_counter()
     orc = oracle_averages(wl, steps)
     return {"workload": "bounded RF discharge 2e5 + 2e5, %d steps, averages over the last "
@@ -305,11 +306,13 @@ def long_run_study(fs, torch, workloads, steps, sub_steps):
     `steps` steps, and the FP64 GPU path against the oracle at the 1e5-per-species
     subsample over `sub_steps` steps, with the seed + 1 floors."""
     half = steps // 2
-    wl = workloads.long_c5(avg_start=half)
+    wl = workloads.long_c5(avg_start=half, sort_mode=SORT)
     r64 = _averages(fs, torch, wl, "fp64", steps)
     r32 = _averages(fs, torch, wl, "fp32_offset", steps)
-    s1 = _averages(fs, torch, workloads.long_c5(avg_start=half, seed=1), "fp64", steps)
-    sub = workloads.long_c5(n_e0=100_000, n_i0=100_000, avg_start=sub_steps // 2)
+    s1 = _averages(fs, torch, workloads.long_c5(avg_start=half, seed=1, sort_mode=SORT), "fp64",
+                   steps)
+    sub = workloads.long_c5(n_e0=100_000, n_i0=100_000, avg_start=sub_steps // 2,
+                            sort_mode=SORT)
     g = _averages(fs, torch, sub, "fp64", sub_steps)
     g1 = _averages(fs, torch, dict(sub, seed=1), "fp64", sub_steps)
     t0 = time.perf_counter()
@@ -443,6 +446,10 @@ def main():
                          "byte counters of rocprofv3")
     ap.add_argument("--progress", type=int, default=0,
                     help="report every N warm-up steps on stderr (for slow profiled runs)")
+    ap.add_argument("--sort", choices=["lag", "counting"], default="lag",
+                    help="sort of the headline, FP64, long-run and batched paths: the "
+                         "counting sort keyed on the cell at the start of the step (lag) "
+                         "or after the push (counting); the other one is timed as a path")
     args = ap.parse_args()
     global PROGRESS_STEPS
     PROGRESS_STEPS = max(0, args.progress)
@@ -468,22 +475,39 @@ def main():
     def log(m):
         print("bench: " + m, file=sys.stderr, flush=True)
 
-    large = workloads.large_c3()
-    log("FP32 cell+offset, large discharge, %d steps after %d" % (args.steps, args.warmup))
+    global SORT
+    SORT = args.sort
+    other = "counting" if SORT == "lag" else "lag"
+    large = workloads.large_c3(sort_mode=SORT)
+    log("FP32 cell+offset, large discharge, %s sort, %d steps after %d"
+        % (SORT, args.steps, args.warmup))
     head = run_path(fs, torch, large, "fp32_offset", args.steps, args.warmup)
     paths = {}
     if not args.skip_paths:
         log("FP64, large discharge")
         r64 = run_path(fs, torch, large, "fp64", args.path_steps, args.warmup)
         paths["fp64"] = r64
+        log("%s sort, large discharge, FP32" % other)
+        paths[other + "_sort_fp32"] = run_path(fs, torch, workloads.large_c3(sort_mode=other),
+                                               "fp32_offset", args.path_steps, args.warmup)
         log("unsorted variant, large discharge, FP32")
         paths["unsorted_fp32"] = run_path(fs, torch, workloads.large_c3(sort_mode="none"),
                                           "fp32_offset", args.path_steps, args.warmup)
+        # the paper's in-place fine sort against its sorting-cell size (N_gc = G + 1 grid
+        # points per sorting cell, the paper's study of cycle time against N_gc)
+        fine = {}
+        for g in (1, 2, 4, 8, 16):
+            log("paper's fine sort, sorting cells of %d grid cells, FP32" % g)
+            r = run_path(fs, torch, workloads.large_c3(sort_mode="fine",
+                                                       grid_points_per_sort_cell=g + 1),
+                         "fp32_offset", args.path_steps // 2, args.warmup, eager=False)
+            fine["N_gc=%d" % (g + 1)] = r
+        paths["fine_sort_fp32"] = fine
         log("long-run discharge at full size, FP32")
-        paths["long_run_fp32"] = run_path(fs, torch, workloads.long_c5(), "fp32_offset",
-                                          args.path_steps // 2, args.warmup)
+        paths["long_run_fp32"] = run_path(fs, torch, workloads.long_c5(sort_mode=SORT),
+                                          "fp32_offset", args.path_steps // 2, args.warmup)
         log("batched scan")
-        batch = workloads.batched_c4(scale=args.batched_scale)
+        batch = [dict(w, sort_mode=SORT) for w in workloads.batched_c4(scale=args.batched_scale)]
         # the hottest discharges of the scan (55-95 Pa, 400-490 V, < 2.5 cm) more than
         # double their ion count within a few hundred steps
         tuning, tune_rep = None, None
@@ -549,6 +573,8 @@ def main():
         "config": {"workload": "large single discharge: 4096 cells (20 cm), 1e7 electrons + "
                                "1e7 ions, Te 2 eV, 300 V at 13.56 MHz, 5 Pa Ar-like MCC, "
                                "sort every step, FP32 cell+offset with FP64 Poisson",
+                   "sort": {"lag": "counting sort by the cell at the start of the step",
+                            "counting": "counting sort by the cell after the push"}[SORT],
                    "particles": 20_000_000, "n_cells": 4096,
                    "window": "steps %d..%d after the load" % (args.warmup + 1,
                                                               args.warmup + args.steps),

@@ -30,8 +30,6 @@ def flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
             # IEEE operations exactly as written: no contraction into FMA
             "-ffp-contract=off",
-            # hardware float atomics for the LDS / far-mover deposits
-            "-munsafe-fp-atomics",
             # no packed FP32 instructions
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]

@@ -609,6 +609,39 @@ __global__ __launch_bounds__(kCombineNodes * kCombineLanes) void k_combine(
     sim.ds[s.ds].w[s.sp][j] = static_cast<double>(sum + s.far_w[j]) * s.dep_inv;
 }
 
+// Exclusive scan of kV values per thread over the workgroup in one pass (the order of
+// block_exclusive_scan for each); lds holds kV * (blockDim / 64 + 1) doubles.
+template <int kV>
+__device__ __forceinline__ void block_exclusive_scan_n(double (&v)[kV], double* lds,
+                                                       double (&total)[kV]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double inc[kV];
+#pragma unroll
+  for (int q = 0; q < kV; ++q) {
+    inc[q] = wave_inclusive_scan(v[q]);
+    if (lane == 63) lds[q * (kSolveWG / 64 + 1) + w] = inc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < kV) {
+    double* l = lds + threadIdx.x * (kSolveWG / 64 + 1);
+    double r = 0.0;
+    for (int i = 0; i < nw; ++i) {
+      const double t = l[i];
+      l[i] = r;
+      r = r + t;
+    }
+    l[nw] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kV; ++q) {
+    const double* l = lds + q * (kSolveWG / 64 + 1);
+    total[q] = l[nw];
+    v[q] = l[w] + (inc[q] - v[q]);
+  }
+  __syncthreads();
+}
+
 // ====================================================================================
 // k_solve: one workgroup per discharge.  The finite-difference Poisson system of eq.
 // poisson_normalized (Sec. 3.5) with Phi_0 = V(t_n), Phi_N = 0 (or periodic, mean charge
@@ -624,95 +657,87 @@ __global__ __launch_bounds__(kCombineNodes * kCombineLanes) void k_combine(
 // for Phi_0 = 0), the plate holds q - E_0, and Phi_0 = V_s + (q - E_0) / C gives
 // Phi_0 = (V_s + (q - sigma_z) / C) / (1 + 1 / (N C)).
 // The step's net charge, field energy and electrode potential are kept for diagnostics.
+// Two workgroup-wide scans: one over rho (its prefix gives R; the totals of rho_k and
+// k rho_k give sum_j R_j, hence s_0), one over the slopes (Phi and the field energy).
 // ====================================================================================
 __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ simp,
                                                     int init_mode) {
   const SimDev& sim = *simp;
   const DischargeDev dd = sim.ds[blockIdx.x];
-  __shared__ double lds_d[kSolveWG / 64 + 1];
-  __shared__ double sv[kMaxCells + 1];  // rho_j, then R_j, then the slope s_j
+  __shared__ double lds_n[3 * (kSolveWG / 64 + 1)];
+  __shared__ double sv[kMaxCells + 1];  // rho_j, then the slope s_j
   const unsigned long long step = init_mode ? 0ull : *sim.step;
   const int N = dd.n_cells;
   const int nn = dd.n_nodes;
   const double GM* we = dd.w[0];
   const double GM* wi = dd.w[1];
   const int tid = threadIdx.x;
-  // thread tid owns the nodes [lo, hi); the node values stay in LDS through the solve
+  // thread tid owns the nodes [lo, hi) and the cells [lo, hc)
   const int per = (nn + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
   const int lo = tid * per;
   const int hi = min(lo + per, nn);
-  for (int j = lo; j < hi; ++j) sv[j] = wi[j] - we[j];
+  const int hc = min(hi, N);
   const double rho_wall0 = wi[0] - we[0];
   const double rho_wallN = dd.periodic ? 0.0 : wi[N] - we[N];
-  const int hc = min(hi, N);  // the thread's cells
-  double total;
-  double sum_rho;
-  {
-    double part = 0.0;
-    for (int j = lo; j < hi; ++j) part += sv[j];
-    sum_rho = block_sum_fixed(part, lds_d);
-  }
-  // mean charge (periodic only)
-  double mean = 0.0;
-  if (dd.periodic) {
-    double part = 0.0;
-    for (int j = lo; j < hc; ++j) part += sv[j];
-    block_exclusive_scan(part, lds_d, total);
-    mean = total / static_cast<double>(N);
-  }
-  // R_j = sum_{k=1..j} (rho_k - mean), j = 0..N-1
-  {
-    double part = 0.0;
-    for (int j = max(lo, 1); j < hc; ++j) part += sv[j] - mean;
-    double run = block_exclusive_scan(part, lds_d, total);
-    for (int j = lo; j < hc; ++j) {
-      if (j >= 1) run += sv[j] - mean;
-      sv[j] = run;
+  // One pass over the charge: the net charge of all nodes, and over the cells 1..N-1 the
+  // sums of rho_k and of k rho_k, whose prefixes give R_j = sum_{k=1..j} (rho_k - mean)
+  // and sum_j R_j = N P - K - mean N (N - 1) / 2 (P, K their totals) without a scan of R.
+  double v3[3] = {0.0, 0.0, 0.0}, t3[3];
+  for (int j = lo; j < hi; ++j) {
+    const double r = wi[j] - we[j];
+    sv[j] = r;
+    v3[2] += r;
+    if (j >= 1 && j < N) {
+      v3[0] += r;
+      v3[1] += static_cast<double>(j) * r;
     }
   }
-  double sum_r;
-  {
-    double part = 0.0;
-    for (int j = lo; j < hc; ++j) part += sv[j];
-    block_exclusive_scan(part, lds_d, sum_r);
-  }
+  block_exclusive_scan_n<3>(v3, lds_n, t3);
+  const double sum_rho = t3[2];
+  // mean charge of the cells (periodic only)
+  const double mean = dd.periodic ? (rho_wall0 + t3[0]) / static_cast<double>(N) : 0.0;
+  const double Nd = static_cast<double>(N);
+  const double sum_r = Nd * t3[0] - t3[1] - mean * Nd * (Nd - 1.0) * 0.5;
   const double vs = dd.periodic ? 0.0 : dd.vhat_amp * sin(dd.phase_per_step * static_cast<double>(step));
   double a = vs;
   double q = 0.0;
   if (dd.cap_norm > 0.0) {
-    const double sigma_z = -(sum_r / static_cast<double>(N)) - rho_wall0;
+    const double sigma_z = -(sum_r / Nd) - rho_wall0;
     if (init_mode) {
-      q = sigma_z + vs / static_cast<double>(N);  // capacitor uncharged at the load
+      q = sigma_z + vs / Nd;  // capacitor uncharged at the load
     } else {
       const SpeciesDev se = sim.sp[dd.spec0];
       const SpeciesDev si = sim.sp[dd.spec0 + 1];
       q = dd.dstat[DS_Q_INIT] + static_cast<double>(si.absorbed[0]) -
           static_cast<double>(se.absorbed[0]) + static_cast<double>(si.emitted[0]);
     }
-    a = (vs + (q - sigma_z) / dd.cap_norm) /
-        (1.0 + 1.0 / (static_cast<double>(N) * dd.cap_norm));
+    a = (vs + (q - sigma_z) / dd.cap_norm) / (1.0 + 1.0 / (Nd * dd.cap_norm));
   }
-  const double s0 = (0.0 - a + sum_r) / static_cast<double>(N);
-  // s_j = s0 - R_j and Phi_j = a + sum_{m<j} s_m
+  const double s0 = (0.0 - a + sum_r) / Nd;
+  // s_j = s0 - R_j into LDS (read across the thread boundary by E below); their sum
+  // (Phi_j = a + sum_{m<j} s_m) and sum of squares (field energy) in one more pass
+  double v2[2] = {0.0, 0.0}, t2[2];
+  {
+    double run = v3[0];  // sum_{k=1..lo-1} rho_k
+    for (int j = lo; j < hc; ++j) {
+      if (j >= 1) run += sv[j];
+      const double sj = s0 - (run - static_cast<double>(j) * mean);
+      sv[j] = sj;
+      v2[0] += sj;
+      v2[1] += sj * sj;
+    }
+  }
+  block_exclusive_scan_n<2>(v2, lds_n, t2);
   double GM* phi = dd.phi;
   {
-    double part = 0.0;
-    for (int j = lo; j < hc; ++j) part += s0 - sv[j];
-    double run = block_exclusive_scan(part, lds_d, total) + a;
+    double run = v2[0] + a;
     for (int j = lo; j < hc; ++j) {
-      const double sj = s0 - sv[j];
-      sv[j] = sj;
       phi[j] = run;
-      run += sj;
+      run += sv[j];
     }
   }
   if (!dd.periodic && tid == 0) phi[N] = 0.0;
-  double field;
-  {
-    double part = 0.0;
-    for (int j = lo; j < hc; ++j) part += sv[j] * sv[j];
-    field = 0.5 * block_sum_fixed(part, lds_d);  // also orders the slope stores above
-  }
+  const double field = 0.5 * t2[1];
   // E from the slopes
   for (int j = lo; j < hi; ++j) {
     double e;
@@ -736,6 +761,7 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
     dd.dstat[DS_Q] = q;
     if (init_mode) dd.dstat[DS_Q_INIT] = q;
   }
+  __syncthreads();  // the phi stores above are read by other threads below
   if (!init_mode && static_cast<long long>(step) >= dd.avg_start) {
     for (int j = tid; j < nn; j += blockDim.x) {
       dd.acc_w[0][j] += we[j];
@@ -1380,7 +1406,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   uint32_t n_cand = 0;  // candidates of this wave so far (wave-uniform)
   auto load = [&](Part<P>& q, uint32_t i) { q.load(in, i); };
 
-  // Push, walls, EEDF and the null-collision test: common to both kinds of tile.
   // Push, walls (reflection, absorption, emission), EEDF, energy sums and the
   // null-collision test: common to both kinds of tile.
   // ek: the lagged sort's window slot of the record's present cell (cell tiles only)
@@ -1615,15 +1640,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       // integer atomics: exact in any order; the LDS pipe absorbs the same-slot conflicts).
       // Lagged: the deposit slot is the post-push cell's, not the scatter slot.
       if constexpr (kLag) {
-        if (st == 0) {
-          const int kd = window_slot(s, tile, d);
-          if (kd >= 0) {
-            atomicAdd(&sh.cnt[kd], 1u);
-            atomicAdd(&sh.dep[lane & (kDepCopies - 1)][kd], right_weight<P>(s, pos));
-          } else {
-            far_deposit<P>(s, d, pos);
-          }
-        }
+        // the slot's count: one LDS add per group of lanes that share the slot
+        const int kd = st == 0 ? window_slot(s, tile, d) : -1;
+        const bool dn = kd >= 0;
+        const unsigned long long md = match_key_few(kd, dn);
+        if (dn && (md & lt) == 0ull) atomicAdd(&sh.cnt[kd], static_cast<uint32_t>(__popcll(md)));
+        if (dn) atomicAdd(&sh.dep[lane & (kDepCopies - 1)][kd], right_weight<P>(s, pos));
+        else if (st == 0) far_deposit<P>(s, d, pos);
       } else {
         if (near) atomicAdd(&sh.dep[lane & (kDepCopies - 1)][k], right_weight<P>(s, pos));
       }
@@ -1783,7 +1806,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // workgroup takes a part of the candidates in input order (the tiles' waves' lists one
 // after the other), 256 at a time, so the collision path runs on full waves:
 // * an electron tile's list (a few thousand candidates) by one workgroup (splitting it
-//   over two was measured slower);
+//   over several was measured slower);
 // * the ion tiles' lists (a handful of candidates each) up to kIonGroup tiles at a time
 //   when there are many: every workgroup pays the collision path's long dependent chain
 //   once per pass, however few lanes it has.
@@ -1991,6 +2014,7 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
   const unsigned long long step = *sim.step;
   const int q = static_cast<int>((step + 1ull) & 1ull);
   const int nt = se.n_tiles + se.n_tail;
+  const SpeciesDev sion = sim.sp[dd.spec0 + 1];
   // thread s (s < 2) settles species s: its counters are loaded before the scan, so their
   // latency overlaps it (nothing in this kernel writes them before they are used)
   uint32_t n_surv = 0u, nid = 0u;
@@ -2002,7 +2026,6 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
   const uint32_t B = array_exclusive_scan_to(se.birth_cnt, se.birth_base, nt, lds);
   // electrons emitted by absorbed ions follow the ionisation births, in the order of their
   // parent ions' input index ((tile, wave) units in order, each list in input order)
-  const SpeciesDev sion = sim.sp[dd.spec0 + 1];
   const int nu_i = (sion.n_tiles + sion.n_tail) * kWaves;
   uint32_t E = 0u;
   if (sion.t_see) E = array_exclusive_scan_to(sion.em_cnt, sion.em_base, nu_i, lds);
@@ -2028,80 +2051,121 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     *s.next_id = nid + fit;
     *s.births += fit;
   }
-  // The step's per-tile sums of both species, combined in a fixed order (each thread over
-  // its tiles in order, a butterfly inside each wave, then the waves in order): the
-  // cumulative wall tallies and, on energy steps, the kinetic energies and momentum.
+  // The step's per-tile sums of both species (k_main's TileStats, 64 bytes: ke, mom,
+  // abs_e[2] as doubles, then abs_n[2], emit[2], refl[2], pushed, alive), combined in a
+  // fixed order: the array is read as 16-byte quarters, thread t taking quarters
+  // t, t + B, t + 2B, ... (B threads, a multiple of 4, so a thread always holds the same
+  // quarter q = t mod 4 and the loads are contiguous across the wave); a butterfly over
+  // the lanes of one quarter, then the waves in order.  The totals: cumulative wall
+  // tallies and, on energy steps, the kinetic energies and momentum.
+  static_assert(sizeof(TileStats) == 64, "TileStats is read as four 16-byte quarters");
   constexpr int kD = 4, kU = 8;
   __shared__ double wd[2][kSolveWG / 64][kD];
   __shared__ uint32_t wu[2][kSolveWG / 64][kU];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int quarter = lane & 3;
+#pragma unroll
   for (int sp = 0; sp < 2; ++sp) {
     const SpeciesDev s = sim.sp[dd.spec0 + sp];
-    const int ntiles = s.n_tiles + s.n_tail;
-    double d[kD] = {0.0, 0.0, 0.0, 0.0};
-    uint32_t u[kU] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-      const TileStats ts = s.tstats[t];
-      d[0] += ts.ke;
-      d[1] += ts.mom;
-      d[2] += ts.abs_e[0];
-      d[3] += ts.abs_e[1];
-      u[0] += ts.abs_n[0];
-      u[1] += ts.abs_n[1];
-      u[2] += ts.emit[0];
-      u[3] += ts.emit[1];
-      u[4] += ts.refl[0];
-      u[5] += ts.refl[1];
-      u[6] += ts.pushed;
-      u[7] += ts.alive;
+    const int nq = 4 * (s.n_tiles + s.n_tail);
+    const uint4 GM* qa = reinterpret_cast<const uint4 GM*>(s.tstats);
+    double x0 = 0.0, x1 = 0.0;                 // quarters 0, 1: two doubles
+    uint32_t y0 = 0u, y1 = 0u, y2 = 0u, y3 = 0u;  // quarters 2, 3: four counts
+    constexpr int kQ = 4;  // quarters of one thread loaded at once
+    for (int c0 = static_cast<int>(threadIdx.x); c0 < nq; c0 += kQ * static_cast<int>(blockDim.x)) {
+      uint4 v[kQ];
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        const int c = c0 + k * static_cast<int>(blockDim.x);
+        v[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (c < nq) v[k] = qa[c];
+      }
+#pragma unroll
+      for (int k = 0; k < kQ; ++k) {
+        if (quarter < 2) {
+          x0 += __hiloint2double(static_cast<int>(v[k].y), static_cast<int>(v[k].x));
+          x1 += __hiloint2double(static_cast<int>(v[k].w), static_cast<int>(v[k].z));
+        } else {
+          y0 += v[k].x;
+          y1 += v[k].y;
+          y2 += v[k].z;
+          y3 += v[k].w;
+        }
+      }
     }
+    // lanes l, l ^ 4, ..., l ^ 60 hold the same quarter
 #pragma unroll
-    for (int k = 0; k < kD; ++k) d[k] = wave_sum(d[k]);
-#pragma unroll
-    for (int k = 0; k < kU; ++k) u[k] = wave_sum(u[k]);
+    for (int o = 4; o < 64; o <<= 1) {
+      x0 += __shfl_xor(x0, o, 64);
+      x1 += __shfl_xor(x1, o, 64);
+      y0 += __shfl_xor(y0, o, 64);
+      y1 += __shfl_xor(y1, o, 64);
+      y2 += __shfl_xor(y2, o, 64);
+      y3 += __shfl_xor(y3, o, 64);
+    }
     if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < kD; ++k) wd[sp][wv][k] = d[k];
-#pragma unroll
-      for (int k = 0; k < kU; ++k) wu[sp][wv][k] = u[k];
+      wd[sp][wv][0] = x0;  // ke
+      wd[sp][wv][1] = x1;  // mom
+    } else if (lane == 1) {
+      wd[sp][wv][2] = x0;  // abs_e[0]
+      wd[sp][wv][3] = x1;  // abs_e[1]
+    } else if (lane == 2) {
+      wu[sp][wv][0] = y0;  // abs_n[0]
+      wu[sp][wv][1] = y1;  // abs_n[1]
+      wu[sp][wv][2] = y2;  // emit[0]
+      wu[sp][wv][3] = y3;  // emit[1]
+    } else if (lane == 3) {
+      wu[sp][wv][4] = y0;  // refl[0]
+      wu[sp][wv][5] = y1;  // refl[1]
+      wu[sp][wv][6] = y2;  // pushed
+      wu[sp][wv][7] = y3;  // alive
     }
   }
   // The last discharge's workgroup advances the step counter (every workgroup read it at
   // its start); the kernel boundary publishes it to k_finalize and the next step.
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const bool energy = diag_step(dd, step);
-    double mom = 0.0;
-    for (int sp = 0; sp < 2; ++sp) {
-      const SpeciesDev s = sim.sp[dd.spec0 + sp];
-      double d[kD] = {0.0, 0.0, 0.0, 0.0};
-      unsigned long long u[kU] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
-      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
-        for (int k = 0; k < kD; ++k) d[k] += wd[sp][w][k];
-        for (int k = 0; k < kU; ++k) u[k] += wu[sp][w][k];
-      }
-      s.absorbed[0] += u[0];
-      s.absorbed[1] += u[1];
-      s.absorbed_energy[0] += d[2];
-      s.absorbed_energy[1] += d[3];
-      s.emitted[0] += u[2];
-      s.emitted[1] += u[3];
-      s.reflected[0] += u[4];
-      s.reflected[1] += u[5];
-      *s.psteps += u[6];
-      // lagged sort: the output holds a dead record for every counted slot whose particle
-      // did not survive the push
-      const uint32_t slots = s.n_sorted[(step + 1ull) & 1ull];
-      s.n_holes[(step + 1ull) & 1ull] =
-          s.mode == kModeLag && slots > u[7] ? slots - static_cast<uint32_t>(u[7]) : 0u;
-      if (energy) {
-        const double ak = fabs(s.kappa);
-        dd.dstat[DS_KIN_E + sp] = d[0] / (2.0 * ak);
-        mom += d[1] / ak;
-      }
+  const bool energy = diag_step(dd, step);
+  __shared__ double mom_sp[2];
+  if (threadIdx.x < 2) {
+    // thread sp settles species sp: the waves' sums in order, then every counter it
+    // updates is loaded before the first store, so the loads are in flight together
+    const int sp = static_cast<int>(threadIdx.x);
+    const SpeciesDev s = sim.sp[dd.spec0 + sp];
+    double d[kD] = {0.0, 0.0, 0.0, 0.0};
+    unsigned long long u[kU] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+      for (int k = 0; k < kD; ++k) d[k] += wd[sp][w][k];
+      for (int k = 0; k < kU; ++k) u[k] += wu[sp][w][k];
     }
+    const int nq = static_cast<int>((step + 1ull) & 1ull);
+    const unsigned long long ab0 = s.absorbed[0], ab1 = s.absorbed[1];
+    const double ae0 = s.absorbed_energy[0], ae1 = s.absorbed_energy[1];
+    const unsigned long long em0 = s.emitted[0], em1 = s.emitted[1];
+    const unsigned long long rf0 = s.reflected[0], rf1 = s.reflected[1];
+    const unsigned long long ps = *s.psteps;
+    const uint32_t slots = s.n_sorted[nq];
+    s.absorbed[0] = ab0 + u[0];
+    s.absorbed[1] = ab1 + u[1];
+    s.absorbed_energy[0] = ae0 + d[2];
+    s.absorbed_energy[1] = ae1 + d[3];
+    s.emitted[0] = em0 + u[2];
+    s.emitted[1] = em1 + u[3];
+    s.reflected[0] = rf0 + u[4];
+    s.reflected[1] = rf1 + u[5];
+    *s.psteps = ps + u[6];
+    // lagged sort: the output holds a dead record for every counted slot whose particle
+    // did not survive the push
+    s.n_holes[nq] = s.mode == kModeLag && slots > u[7] ? slots - static_cast<uint32_t>(u[7]) : 0u;
     if (energy) {
-      dd.dstat[DS_MOM] = mom;
+      const double ak = fabs(s.kappa);
+      dd.dstat[DS_KIN_E + sp] = d[0] / (2.0 * ak);
+      mom_sp[sp] = d[1] / ak;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (energy) {
+      dd.dstat[DS_MOM] = mom_sp[0] + mom_sp[1];
       *dd.energy_step = step;
     }
     const uint32_t done = atomicAdd(sim.fin_count, 1u);

@@ -65,7 +65,8 @@ def test_general_sort_of_unsorted_state(fspic, oracle_mod, precision):
     sim.close()
 
 
-def test_batched_discharges_match_oracle_each(fspic, oracle_mod):
+@pytest.mark.parametrize("sort", ["counting", "lag"])
+def test_batched_discharges_match_oracle_each(fspic, oracle_mod, sort):
     """Three discharges of the batched scan (particle counts scaled down) in one launch per
     kernel.  Free-running from each side's own load for 4 steps the permutation matches
     every discharge's oracle exactly; the node weights match to 1e-10 of max w, not 1e-12,
@@ -74,8 +75,8 @@ def test_batched_discharges_match_oracle_each(fspic, oracle_mod):
     differently by ~N eps relative in E, and the positions accumulate it.  Then one step
     from seeded states set into both sides meets the 1e-12 bar for every discharge, and
     discharge 1 run alone gives the same particles as inside the batch."""
-    wls = workloads.batched_c4(n_discharges=3, scale=0.01)
-    print("batched", [(w["n_cells"], w["n_e0"]) for w in wls], flush=True)
+    wls = [dict(w, sort_mode=sort) for w in workloads.batched_c4(n_discharges=3, scale=0.01)]
+    print("batched", sort, [(w["n_cells"], w["n_e0"]) for w in wls], flush=True)
     sim = fspic.Simulation(wls, "fp64")
     orcs = []
     for wl in wls:
@@ -157,11 +158,13 @@ def bitwise_equal_diagnostics(da, db, label):
         assert getattr(da, f) == getattr(db, f), (label, f)
 
 
+@pytest.mark.parametrize("sort", ["counting", "lag"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
-def test_graph_replay_bitwise_equals_eager(fspic, precision):
+def test_graph_replay_bitwise_equals_eager(fspic, precision, sort):
     """30 ionising steps replayed from a captured HIP graph of 10 steps and launched one
     by one give the same state bit for bit."""
-    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0, diag_every=1, avg_start=0)
+    wl = workloads.rf_c2(n_e0=20000, n_i0=20000, gas_pa=30.0, diag_every=1, avg_start=0,
+                         sort_mode=sort)
     a = fspic.Simulation(wl, precision)
     b = fspic.Simulation(wl, precision)
     b.set_graph(10)
@@ -175,13 +178,15 @@ def test_graph_replay_bitwise_equals_eager(fspic, precision):
     b.close()
 
 
+@pytest.mark.parametrize("sort", ["counting", "lag"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
-def test_same_seed_twice_bitwise(fspic, precision):
+def test_same_seed_twice_bitwise(fspic, precision, sort):
     """The same seed run twice (400 ionising steps of the bounded discharge) gives the same
     particles, node weights and tallies bit for bit: charge is summed in fixed point and
     every floating-point sum in a fixed order, so nothing depends on the order in which
     the GPU schedules the work."""
-    wl = workloads.rf_c2(n_e0=50000, n_i0=50000, gas_pa=30.0, diag_every=7, avg_start=100)
+    wl = workloads.rf_c2(n_e0=50000, n_i0=50000, gas_pa=30.0, diag_every=7, avg_start=100,
+                         sort_mode=sort)
     runs = []
     for _ in range(2):
         sim = fspic.Simulation(wl, precision)
@@ -199,8 +204,9 @@ def test_same_seed_twice_bitwise(fspic, precision):
     assert sum(da.births) > 0  # the run ionises
 
 
+@pytest.mark.parametrize("sort", ["counting", "lag"])
 @pytest.mark.parametrize("precision", ["fp32_offset", "fp64"])
-def test_full_size_large_discharge_one_step(fspic, oracle_mod, precision):
+def test_full_size_large_discharge_one_step(fspic, oracle_mod, precision, sort):
     """The large single discharge at full size (4096 cells, 1e7 + 1e7 particles), with the
     tile geometry the benchmark times, one step from a seeded state (electron spread 2.2
     cells per step, a births tail of 1000) against the oracle over every particle.  About
@@ -208,29 +214,30 @@ def test_full_size_large_discharge_one_step(fspic, oracle_mod, precision):
     other way at a node where the fixed-point and the FP64 charge sums differ in the last
     bits, which could move a channel decision of a candidate that close to a channel
     boundary: at most one flip is allowed; the FP64 path must match exactly."""
-    wl = workloads.large_c3()
+    wl = workloads.large_c3(sort_mode=sort)
     fp32 = precision == "fp32_offset"
-    print("full size", precision, flush=True)
+    print("full size", precision, sort, flush=True)
     st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
                                    seed=23, vth=(2.2, 0.01), tail=(1000, 1000))
     one_step(fspic, oracle_mod, wl, st, precision, coll_slack=1 if fp32 else 0,
-             label="full " + precision)
+             label="full %s %s" % (precision, sort))
 
 
+@pytest.mark.parametrize("sort", ["counting", "lag"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
-def test_full_size_long_run_one_step(fspic, oracle_mod, precision):
+def test_full_size_long_run_one_step(fspic, oracle_mod, precision, sort):
     """The long run's discharge at full size (8192 cells, 3.2e7 + 3.2e7 particles, 20 Pa)
     with its default geometry: one-cell tiles for both species, so 8192 + 16 tail ion
     tiles and the MCC pass groups the ion lists four at a time; about 1e7 collision
     candidates.  One step from a seeded state against the oracle over every particle (the
     FP32 layout may flip one channel decision, as in the large discharge)."""
-    wl = workloads.long_c5()
+    wl = workloads.long_c5(sort_mode=sort)
     fp32 = precision == "fp32_offset"
-    print("long run full size", precision, flush=True)
+    print("long run full size", precision, sort, flush=True)
     st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), precision,
                                    seed=29, vth=(2.2, 0.01), tail=(1000, 1000))
     one_step(fspic, oracle_mod, wl, st, precision, coll_slack=1 if fp32 else 0,
-             label="long " + precision)
+             label="long %s %s" % (precision, sort))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
