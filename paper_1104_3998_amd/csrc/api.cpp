@@ -252,6 +252,9 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       S.reflected = cv.take<unsigned long long>(2);
       S.psteps = cv.take<unsigned long long>(1);
       S.tstats = cv.take<TileStats>(static_cast<size_t>(ntt));
+      S.ev_bits = cv.take<uint32_t>((static_cast<size_t>(ntt) + 31) / 32);
+      S.tcount = cv.take<uint2>(static_cast<size_t>(ntt));
+      S.tke = cv.take<double>(2 * static_cast<size_t>(ntt));
       S.t_refl = s == 0 ? word_threshold(c.refl_e) : 0u;
       S.t_see = s == 1 ? word_threshold(c.see_gamma) : 0u;
       S.vth_see = see_spread(c, k);

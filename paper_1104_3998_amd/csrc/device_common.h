@@ -478,46 +478,54 @@ __device__ __forceinline__ T block_sum_fixed(T v, T* lds) {
   return r;
 }
 
-// Exclusive scan of src[0..n) into dst[0..n) by one workgroup (no copy of src to dst
-// first); returns the total.  The caller orders any earlier writes of src with a barrier.
+// Exclusive scan of src[0..n) into dst[0..n) by one workgroup (dst may be src: in place);
+// returns the total.  Thread t takes the contiguous part [t per, (t + 1) per); parts of
+// up to kScanPer elements are read into registers at once, so that their loads are in
+// flight together.  The caller orders any earlier writes of src with a barrier; the
+// barrier at the end makes the workgroup's own stores visible to it (its waves share one
+// CU; no device-scope fence, which on this GPU writes back the whole L2).
+constexpr int kScanPer = 16;
 template <class T, class Ptr>
 __device__ T array_exclusive_scan_to(Ptr src, Ptr dst, int n, T* lds) {
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per;
   const int hi = lo + per < n ? lo + per : n;
   T sum = T(0);
-  for (int i = lo; i < hi; ++i) sum = sum + src[i];
   T total;
-  T run = block_exclusive_scan(sum, lds, total);
-  for (int i = lo; i < hi; ++i) {
-    const T v = src[i];
-    dst[i] = run;
-    run = run + v;
+  if (per <= kScanPer) {
+    T v[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = T(0);
+      if (lo + k < hi) v[k] = src[lo + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) sum = sum + v[k];
+    T run = block_exclusive_scan(sum, lds, total);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (lo + k < hi) dst[lo + k] = run;
+      run = run + v[k];
+    }
+  } else {
+    for (int i = lo; i < hi; ++i) sum = sum + src[i];
+    T run = block_exclusive_scan(sum, lds, total);
+    for (int i = lo; i < hi; ++i) {
+      const T v = src[i];
+      dst[i] = run;
+      run = run + v;
+    }
   }
   __syncthreads();
   return total;
 }
 
-// In-place exclusive scan of a[0..n) by one workgroup; returns the total.  The barriers
-// make the workgroup's own global stores visible to it (its waves share one CU); no
-// device-scope fence, which on this GPU writes back the whole L2.
+// In-place exclusive scan of a[0..n) by one workgroup; returns the total (a barrier first
+// orders the workgroup's earlier writes of a).
 template <class T, class Ptr>
 __device__ T array_exclusive_scan(Ptr a, int n, T* lds) {
   __syncthreads();
-  const int per = (n + blockDim.x - 1) / blockDim.x;
-  const int lo = threadIdx.x * per;
-  const int hi = lo + per < n ? lo + per : n;
-  T sum = T(0);
-  for (int i = lo; i < hi; ++i) sum = sum + a[i];
-  T total;
-  T run = block_exclusive_scan(sum, lds, total);
-  for (int i = lo; i < hi; ++i) {
-    const T v = a[i];
-    a[i] = run;
-    run = run + v;
-  }
-  __syncthreads();
-  return total;
+  return array_exclusive_scan_to<T>(a, a, n, lds);
 }
 
 }  // namespace fspic

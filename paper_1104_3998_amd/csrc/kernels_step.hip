@@ -683,13 +683,29 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
   // sums of rho_k and of k rho_k, whose prefixes give R_j = sum_{k=1..j} (rho_k - mean)
   // and sum_j R_j = N P - K - mean N (N - 1) / 2 (P, K their totals) without a scan of R.
   double v3[3] = {0.0, 0.0, 0.0}, t3[3];
-  for (int j = lo; j < hi; ++j) {
-    const double r = wi[j] - we[j];
-    sv[j] = r;
-    v3[2] += r;
-    if (j >= 1 && j < N) {
-      v3[0] += r;
-      v3[1] += static_cast<double>(j) * r;
+  constexpr int kB = 8;  // nodes of a thread read at once (their loads in flight together)
+  for (int j0 = lo; j0 < hi; j0 += kB) {
+    double a[kB], b[kB];
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      a[k] = 0.0;
+      b[k] = 0.0;
+      if (j0 + k < hi) {
+        a[k] = wi[j0 + k];
+        b[k] = we[j0 + k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kB; ++k) {
+      const int j = j0 + k;
+      if (j >= hi) break;
+      const double r = a[k] - b[k];
+      sv[j] = r;
+      v3[2] += r;
+      if (j >= 1 && j < N) {
+        v3[0] += r;
+        v3[1] += static_cast<double>(j) * r;
+      }
     }
   }
   block_exclusive_scan_n<3>(v3, lds_n, t3);
@@ -763,10 +779,32 @@ __global__ __launch_bounds__(kSolveWG) void k_solve(const SimDev* __restrict__ s
   }
   __syncthreads();  // the phi stores above are read by other threads below
   if (!init_mode && static_cast<long long>(step) >= dd.avg_start) {
-    for (int j = tid; j < nn; j += blockDim.x) {
-      dd.acc_w[0][j] += we[j];
-      dd.acc_w[1][j] += wi[j];
-      dd.acc_phi[j] += phi[j];
+    constexpr int kA = 4;  // nodes of a thread updated at once
+    const int B = static_cast<int>(blockDim.x);
+    for (int j0 = tid; j0 < nn; j0 += kA * B) {
+      double x0[kA], x1[kA], x2[kA], y0[kA], y1[kA], y2[kA];
+#pragma unroll
+      for (int k = 0; k < kA; ++k) {
+        const int j = j0 + k * B;
+        x0[k] = x1[k] = x2[k] = y0[k] = y1[k] = y2[k] = 0.0;
+        if (j < nn) {
+          x0[k] = dd.acc_w[0][j];
+          x1[k] = dd.acc_w[1][j];
+          x2[k] = dd.acc_phi[j];
+          y0[k] = we[j];
+          y1[k] = wi[j];
+          y2[k] = phi[j];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kA; ++k) {
+        const int j = j0 + k * B;
+        if (j < nn) {
+          dd.acc_w[0][j] = x0[k] + y0[k];
+          dd.acc_w[1][j] = x1[k] + y1[k];
+          dd.acc_phi[j] = x2[k] + y2[k];
+        }
+      }
     }
     if (tid == 0) *dd.acc_count += 1ull;
   }
@@ -1141,7 +1179,18 @@ __global__ __launch_bounds__(kSolveWG) void k_scan_base(const SimDev* __restrict
     }
   }
   uint32_t GM* cs = s.cell_start + q * (N + 1);
-  for (int c = threadIdx.x; c < N; c += blockDim.x) cs[c] = s.base[c];
+  {
+    constexpr int kC = 8;  // cells of a thread copied at once
+    const int B = static_cast<int>(blockDim.x);
+    for (int c0 = threadIdx.x; c0 < N; c0 += kC * B) {
+      uint32_t v[kC];
+#pragma unroll
+      for (int k = 0; k < kC; ++k) v[k] = c0 + k * B < N ? s.base[c0 + k * B] : 0u;
+#pragma unroll
+      for (int k = 0; k < kC; ++k)
+        if (c0 + k * B < N) cs[c0 + k * B] = v[k];
+    }
+  }
   if (threadIdx.x == 0) {
     cs[N] = n_surv;
     s.n_sorted[q] = n_surv;
@@ -1778,22 +1827,33 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
   if (tid == 0) {
     if (sh.err) atomicOr(sim.error, sh.err);
+    // the tile's sums, waves in order: energies on energy steps; pushed and surviving
+    // counts; wall events (rare: tiles at the walls) into the tile's event record, marked
+    // in the event bitmap
     TileStats ts{};
-    for (int w = 0; w < kWaves; ++w) {  // waves in order
-      ts.ke += sh.wst[w][0];
-      ts.mom += sh.wst[w][1];
+    double ke = 0.0, mom = 0.0;
+    uint32_t pushed = 0u, alive = 0u;
+    for (int w = 0; w < kWaves; ++w) {
+      ke += sh.wst[w][0];
+      mom += sh.wst[w][1];
       ts.abs_e[0] += sh.wst[w][2];
       ts.abs_e[1] += sh.wst[w][3];
       ts.abs_n[0] += sh.wcnt[w][0];
       ts.abs_n[1] += sh.wcnt[w][1];
-      ts.emit[0] += sh.wcnt[w][2];
-      ts.emit[1] += sh.wcnt[w][3];
       ts.refl[0] += sh.wcnt[w][4];
       ts.refl[1] += sh.wcnt[w][5];
-      ts.pushed += sh.wcnt[w][6];
-      ts.alive += sh.wcnt[w][7];
+      pushed += sh.wcnt[w][6];
+      alive += sh.wcnt[w][7];
     }
-    s.tstats[tile] = ts;
+    if (energy_on) {
+      s.tke[2 * tile] = ke;
+      s.tke[2 * tile + 1] = mom;
+    }
+    s.tcount[tile] = make_uint2(pushed, alive);
+    if (ts.abs_n[0] | ts.abs_n[1] | ts.refl[0] | ts.refl[1]) {
+      s.tstats[tile] = ts;  // emit[] is filled in by k_emit
+      atomicOr(&s.ev_bits[tile >> 5], 1u << (tile & 31));
+    }
   }
   if (eedf_on)
     for (int k = tid; k <= dd.eedf_bins; k += kWG)
@@ -2010,32 +2070,160 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
   const SimDev& sim = *simp;
   const DischargeDev dd = sim.ds[blockIdx.x];
   const SpeciesDev se = sim.sp[dd.spec0];
+  const SpeciesDev sion = sim.sp[dd.spec0 + 1];
   __shared__ uint32_t lds[kSolveWG / 64 + 1];
   const unsigned long long step = *sim.step;
   const int q = static_cast<int>((step + 1ull) & 1ull);
   const int nt = se.n_tiles + se.n_tail;
-  const SpeciesDev sion = sim.sp[dd.spec0 + 1];
-  // thread s (s < 2) settles species s: its counters are loaded before the scan, so their
-  // latency overlaps it (nothing in this kernel writes them before they are used)
-  uint32_t n_surv = 0u, nid = 0u;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // The step's tallies of both species, each combined in a fixed order:
+  // * pushed and surviving particles of every tile (integers: wave sums, then the waves);
+  // * on energy steps, the kinetic energy and momentum of every tile: thread t takes tiles
+  //   t, t + B, ... in order, a butterfly inside each wave, then the waves in order;
+  // * wall events: only the tiles marked in the event bitmap (a few, at the walls).  Each
+  //   event tile gets its rank in tile order from a scan of the bitmap words' bit counts,
+  //   its record goes to that place of an LDS list, and the settling thread adds the list
+  //   in order (past kEvCap entries it reads the rest from global memory in tile order).
+  const bool energy = diag_step(dd, step);
+  constexpr int kD = 2, kU = 2;  // ke, mom | pushed, alive
+  constexpr int kEvCap = 128;
+  __shared__ double wd[2][kSolveWG / 64][kD];
+  __shared__ uint32_t wu[2][kSolveWG / 64][kU];
+  __shared__ TileStats evl[2][kEvCap];
+  __shared__ uint32_t ev_n[2];
+  {
+    const int B = static_cast<int>(blockDim.x);
+    const int tid = static_cast<int>(threadIdx.x);
+    const int ntl[2] = {se.n_tiles + se.n_tail, sion.n_tiles + sion.n_tail};
+    const uint2 GM* tc[2] = {se.tcount, sion.tcount};
+    const uint32_t GM* eb[2] = {se.ev_bits, sion.ev_bits};
+    // the counts of both species and this thread's bitmap words, all loads issued at once
+    constexpr int kT = 8;  // a thread's tiles read at once
+    uint32_t pushed[2] = {0u, 0u}, alive[2] = {0u, 0u};
+    uint32_t word[2] = {0u, 0u};  // bitmap word tid (one per thread up to 32 B tiles)
+    const int nw[2] = {(ntl[0] + 31) / 32, (ntl[1] + 31) / 32};
+    const bool one_word = nw[0] <= B && nw[1] <= B;
+    {
+      uint2 c[2][kT];
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+        for (int k = 0; k < kT; ++k) {
+          c[sp][k] = make_uint2(0u, 0u);
+          if (tid + k * B < ntl[sp]) c[sp][k] = tc[sp][tid + k * B];
+        }
+        if (one_word && tid < nw[sp]) word[sp] = eb[sp][tid];
+      }
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+        for (int k = 0; k < kT; ++k) {
+          pushed[sp] += c[sp][k].x;
+          alive[sp] += c[sp][k].y;
+        }
+        for (int t = tid + kT * B; t < ntl[sp]; t += B) {  // more than kT tiles per thread
+          const uint2 cc = tc[sp][t];
+          pushed[sp] += cc.x;
+          alive[sp] += cc.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesDev s = sp == 0 ? se : sion;
+      double ke = 0.0, mom = 0.0;
+      if (energy)
+        for (int t = tid; t < ntl[sp]; t += B) {
+          ke += s.tke[2 * t];
+          mom += s.tke[2 * t + 1];
+        }
+      const uint32_t ps = __reduce_add_sync(~0ull, pushed[sp]);
+      const uint32_t al = __reduce_add_sync(~0ull, alive[sp]);
+      if (energy) {
+        ke = wave_sum(ke);
+        mom = wave_sum(mom);
+      }
+      if (lane == 0) {
+        wu[sp][wv][0] = ps;
+        wu[sp][wv][1] = al;
+        wd[sp][wv][0] = ke;
+        wd[sp][wv][1] = mom;
+      }
+    }
+    // event tiles: thread t takes bitmap words [t pw, (t + 1) pw) of each species; their
+    // ranks in tile order come from one scan of both species' counts (packed in 16-bit
+    // halves: a species has fewer than 2^16 tiles)
+    const int pw[2] = {(nw[0] + B - 1) / B, (nw[1] + B - 1) / B};
+    uint32_t cnt[2] = {0u, 0u};
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      if (one_word) {
+        cnt[sp] = static_cast<uint32_t>(__popc(word[sp]));
+      } else {
+        const int w0 = min(nw[sp], tid * pw[sp]), w1 = min(nw[sp], w0 + pw[sp]);
+        for (int w = w0; w < w1; ++w) cnt[sp] += static_cast<uint32_t>(__popc(eb[sp][w]));
+      }
+    }
+    uint32_t total;
+    const uint32_t rr = block_exclusive_scan<uint32_t>(cnt[0] | (cnt[1] << 16), lds, total);
+    if (tid == 0) {
+      ev_n[0] = total & 0xFFFFu;
+      ev_n[1] = total >> 16;
+    }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesDev s = sp == 0 ? se : sion;
+      uint32_t r = sp == 0 ? (rr & 0xFFFFu) : (rr >> 16);
+      if (!cnt[sp]) continue;
+      const int w0 = one_word ? tid : min(nw[sp], tid * pw[sp]);
+      const int w1 = one_word ? tid + 1 : min(nw[sp], w0 + pw[sp]);
+      for (int w = w0; w < w1; ++w) {
+        uint32_t bits = one_word ? word[sp] : eb[sp][w];
+        while (bits) {
+          const int t = 32 * w + __ffs(bits) - 1;
+          bits &= bits - 1u;
+          if (r < static_cast<uint32_t>(kEvCap)) evl[sp][r] = s.tstats[t];
+          ++r;
+        }
+      }
+    }
+  }
+  // thread s (s < 2) settles species s: every counter it reads is loaded here, before the
+  // births scan, so that their latency overlaps it (nothing in this kernel writes them
+  // before they are used)
+  uint32_t n_surv = 0u, nid = 0u, slots = 0u;
+  unsigned long long c_births = 0ull, c_ab[2] = {0ull, 0ull}, c_em[2] = {0ull, 0ull};
+  unsigned long long c_rf[2] = {0ull, 0ull}, c_ps = 0ull;
+  double c_ae[2] = {0.0, 0.0};
   if (threadIdx.x < 2) {
-    const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
+    const SpeciesDev s = threadIdx.x == 0 ? se : sion;
     n_surv = s.n_sorted[q];
     nid = *s.next_id;
+    c_births = *s.births;
+    c_ab[0] = s.absorbed[0];
+    c_ab[1] = s.absorbed[1];
+    c_ae[0] = s.absorbed_energy[0];
+    c_ae[1] = s.absorbed_energy[1];
+    c_em[0] = s.emitted[0];
+    c_em[1] = s.emitted[1];
+    c_rf[0] = s.reflected[0];
+    c_rf[1] = s.reflected[1];
+    c_ps = *s.psteps;
+    slots = n_surv;  // the slots of the output, dead records included
   }
-  const uint32_t B = array_exclusive_scan_to(se.birth_cnt, se.birth_base, nt, lds);
+  const uint32_t Bn = array_exclusive_scan_to(se.birth_cnt, se.birth_base, nt, lds);
   // electrons emitted by absorbed ions follow the ionisation births, in the order of their
   // parent ions' input index ((tile, wave) units in order, each list in input order)
   const int nu_i = (sion.n_tiles + sion.n_tail) * kWaves;
   uint32_t E = 0u;
   if (sion.t_see) E = array_exclusive_scan_to(sion.em_cnt, sion.em_base, nu_i, lds);
   if (threadIdx.x < 2) {
-    const SpeciesDev s = sim.sp[dd.spec0 + static_cast<int>(threadIdx.x)];
+    const SpeciesDev s = threadIdx.x == 0 ? se : sion;
     if (threadIdx.x == 0) {
-      se.birth_base[nt] = B;
+      se.birth_base[nt] = Bn;
       if (sion.t_see) sion.em_base[nu_i] = E;
     }
-    uint32_t fit = threadIdx.x == 0 ? B + E : B;
+    uint32_t fit = threadIdx.x == 0 ? Bn + E : Bn;
     const uint32_t room = s.cap > n_surv ? s.cap - n_surv : 0u;
     if (fit > room) {
       fit = room;
@@ -2049,129 +2237,94 @@ __global__ __launch_bounds__(kSolveWG) void k_birth_scan(const SimDev* __restric
     s.fin[1] = nid;
     s.n_total[q] = n_surv + fit;
     *s.next_id = nid + fit;
-    *s.births += fit;
+    *s.births = c_births + fit;
   }
-  // The step's per-tile sums of both species (k_main's TileStats, 64 bytes: ke, mom,
-  // abs_e[2] as doubles, then abs_n[2], emit[2], refl[2], pushed, alive), combined in a
-  // fixed order: the array is read as 16-byte quarters, thread t taking quarters
-  // t, t + B, t + 2B, ... (B threads, a multiple of 4, so a thread always holds the same
-  // quarter q = t mod 4 and the loads are contiguous across the wave); a butterfly over
-  // the lanes of one quarter, then the waves in order.  The totals: cumulative wall
-  // tallies and, on energy steps, the kinetic energies and momentum.
-  static_assert(sizeof(TileStats) == 64, "TileStats is read as four 16-byte quarters");
-  constexpr int kD = 4, kU = 8;
-  __shared__ double wd[2][kSolveWG / 64][kD];
-  __shared__ uint32_t wu[2][kSolveWG / 64][kU];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int quarter = lane & 3;
-#pragma unroll
-  for (int sp = 0; sp < 2; ++sp) {
-    const SpeciesDev s = sim.sp[dd.spec0 + sp];
-    const int nq = 4 * (s.n_tiles + s.n_tail);
-    const uint4 GM* qa = reinterpret_cast<const uint4 GM*>(s.tstats);
-    double x0 = 0.0, x1 = 0.0;                 // quarters 0, 1: two doubles
-    uint32_t y0 = 0u, y1 = 0u, y2 = 0u, y3 = 0u;  // quarters 2, 3: four counts
-    constexpr int kQ = 4;  // quarters of one thread loaded at once
-    for (int c0 = static_cast<int>(threadIdx.x); c0 < nq; c0 += kQ * static_cast<int>(blockDim.x)) {
-      uint4 v[kQ];
-#pragma unroll
-      for (int k = 0; k < kQ; ++k) {
-        const int c = c0 + k * static_cast<int>(blockDim.x);
-        v[k] = make_uint4(0u, 0u, 0u, 0u);
-        if (c < nq) v[k] = qa[c];
-      }
-#pragma unroll
-      for (int k = 0; k < kQ; ++k) {
-        if (quarter < 2) {
-          x0 += __hiloint2double(static_cast<int>(v[k].y), static_cast<int>(v[k].x));
-          x1 += __hiloint2double(static_cast<int>(v[k].w), static_cast<int>(v[k].z));
-        } else {
-          y0 += v[k].x;
-          y1 += v[k].y;
-          y2 += v[k].z;
-          y3 += v[k].w;
+  __syncthreads();
+  __shared__ double mom_sp[2];
+  if (threadIdx.x < 2) {
+    // thread sp settles species sp: the waves' sums in order, the event list in order,
+    // then the counters
+    const int sp = static_cast<int>(threadIdx.x);
+    const SpeciesDev s = sp == 0 ? se : sion;
+    double ke = 0.0, mom = 0.0, ae[2] = {0.0, 0.0};
+    unsigned long long pushed = 0ull, alive = 0ull;
+    unsigned long long ab[2] = {0ull, 0ull}, em[2] = {0ull, 0ull}, rf[2] = {0ull, 0ull};
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
+      ke += wd[sp][w][0];
+      mom += wd[sp][w][1];
+      pushed += wu[sp][w][0];
+      alive += wu[sp][w][1];
+    }
+    auto add_event = [&](const TileStats& ts) {
+      ae[0] += ts.abs_e[0];
+      ae[1] += ts.abs_e[1];
+      ab[0] += ts.abs_n[0];
+      ab[1] += ts.abs_n[1];
+      em[0] += ts.emit[0];
+      em[1] += ts.emit[1];
+      rf[0] += ts.refl[0];
+      rf[1] += ts.refl[1];
+    };
+    const uint32_t m = ev_n[sp];
+    for (uint32_t r = 0; r < m && r < static_cast<uint32_t>(kEvCap); ++r) add_event(evl[sp][r]);
+    if (m > static_cast<uint32_t>(kEvCap)) {  // the rest, in tile order, from global memory
+      const int ntiles = s.n_tiles + s.n_tail;
+      uint32_t r = 0u;
+      for (int w = 0; w < (ntiles + 31) / 32; ++w) {
+        uint32_t bits = s.ev_bits[w];
+        while (bits) {
+          const int t = 32 * w + __ffs(bits) - 1;
+          bits &= bits - 1u;
+          if (r >= static_cast<uint32_t>(kEvCap)) add_event(s.tstats[t]);
+          ++r;
         }
       }
     }
-    // lanes l, l ^ 4, ..., l ^ 60 hold the same quarter
-#pragma unroll
-    for (int o = 4; o < 64; o <<= 1) {
-      x0 += __shfl_xor(x0, o, 64);
-      x1 += __shfl_xor(x1, o, 64);
-      y0 += __shfl_xor(y0, o, 64);
-      y1 += __shfl_xor(y1, o, 64);
-      y2 += __shfl_xor(y2, o, 64);
-      y3 += __shfl_xor(y3, o, 64);
+    s.absorbed[0] = c_ab[0] + ab[0];
+    s.absorbed[1] = c_ab[1] + ab[1];
+    s.absorbed_energy[0] = c_ae[0] + ae[0];
+    s.absorbed_energy[1] = c_ae[1] + ae[1];
+    s.emitted[0] = c_em[0] + em[0];
+    s.emitted[1] = c_em[1] + em[1];
+    s.reflected[0] = c_rf[0] + rf[0];
+    s.reflected[1] = c_rf[1] + rf[1];
+    *s.psteps = c_ps + pushed;
+    // lagged sort: the output holds a dead record for every counted slot whose particle
+    // did not survive the push
+    s.n_holes[q] = s.mode == kModeLag && slots > alive ? slots - static_cast<uint32_t>(alive) : 0u;
+    if (energy) {
+      const double ak = fabs(s.kappa);
+      dd.dstat[DS_KIN_E + sp] = ke / (2.0 * ak);
+      mom_sp[sp] = mom / ak;
     }
-    if (lane == 0) {
-      wd[sp][wv][0] = x0;  // ke
-      wd[sp][wv][1] = x1;  // mom
-    } else if (lane == 1) {
-      wd[sp][wv][2] = x0;  // abs_e[0]
-      wd[sp][wv][3] = x1;  // abs_e[1]
-    } else if (lane == 2) {
-      wu[sp][wv][0] = y0;  // abs_n[0]
-      wu[sp][wv][1] = y1;  // abs_n[1]
-      wu[sp][wv][2] = y2;  // emit[0]
-      wu[sp][wv][3] = y3;  // emit[1]
-    } else if (lane == 3) {
-      wu[sp][wv][4] = y0;  // refl[0]
-      wu[sp][wv][5] = y1;  // refl[1]
-      wu[sp][wv][6] = y2;  // pushed
-      wu[sp][wv][7] = y3;  // alive
+  }
+  __syncthreads();
+  {
+    // the event bitmaps start the next step empty
+    const int tid = static_cast<int>(threadIdx.x), B = static_cast<int>(blockDim.x);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      const SpeciesDev s = sp == 0 ? se : sion;
+      const int nw = (s.n_tiles + s.n_tail + 31) / 32;
+      for (int w = tid; w < nw; w += B)
+        if (s.ev_bits[w]) s.ev_bits[w] = 0u;
     }
   }
   // The last discharge's workgroup advances the step counter (every workgroup read it at
   // its start); the kernel boundary publishes it to k_finalize and the next step.
-  __syncthreads();
-  const bool energy = diag_step(dd, step);
-  __shared__ double mom_sp[2];
-  if (threadIdx.x < 2) {
-    // thread sp settles species sp: the waves' sums in order, then every counter it
-    // updates is loaded before the first store, so the loads are in flight together
-    const int sp = static_cast<int>(threadIdx.x);
-    const SpeciesDev s = sim.sp[dd.spec0 + sp];
-    double d[kD] = {0.0, 0.0, 0.0, 0.0};
-    unsigned long long u[kU] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
-    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) {
-      for (int k = 0; k < kD; ++k) d[k] += wd[sp][w][k];
-      for (int k = 0; k < kU; ++k) u[k] += wu[sp][w][k];
-    }
-    const int nq = static_cast<int>((step + 1ull) & 1ull);
-    const unsigned long long ab0 = s.absorbed[0], ab1 = s.absorbed[1];
-    const double ae0 = s.absorbed_energy[0], ae1 = s.absorbed_energy[1];
-    const unsigned long long em0 = s.emitted[0], em1 = s.emitted[1];
-    const unsigned long long rf0 = s.reflected[0], rf1 = s.reflected[1];
-    const unsigned long long ps = *s.psteps;
-    const uint32_t slots = s.n_sorted[nq];
-    s.absorbed[0] = ab0 + u[0];
-    s.absorbed[1] = ab1 + u[1];
-    s.absorbed_energy[0] = ae0 + d[2];
-    s.absorbed_energy[1] = ae1 + d[3];
-    s.emitted[0] = em0 + u[2];
-    s.emitted[1] = em1 + u[3];
-    s.reflected[0] = rf0 + u[4];
-    s.reflected[1] = rf1 + u[5];
-    *s.psteps = ps + u[6];
-    // lagged sort: the output holds a dead record for every counted slot whose particle
-    // did not survive the push
-    s.n_holes[nq] = s.mode == kModeLag && slots > u[7] ? slots - static_cast<uint32_t>(u[7]) : 0u;
-    if (energy) {
-      const double ak = fabs(s.kappa);
-      dd.dstat[DS_KIN_E + sp] = d[0] / (2.0 * ak);
-      mom_sp[sp] = d[1] / ak;
-    }
-  }
-  __syncthreads();
   if (threadIdx.x == 0) {
     if (energy) {
       dd.dstat[DS_MOM] = mom_sp[0] + mom_sp[1];
       *dd.energy_step = step;
     }
-    const uint32_t done = atomicAdd(sim.fin_count, 1u);
-    if (done == gridDim.x - 1u) {
-      *sim.fin_count = 0u;
-      *sim.step = *sim.step + 1ull;
+    if (gridDim.x == 1u) {
+      *sim.step = step + 1ull;
+    } else {
+      const uint32_t done = atomicAdd(sim.fin_count, 1u);
+      if (done == gridDim.x - 1u) {
+        *sim.fin_count = 0u;
+        *sim.step = step + 1ull;
+      }
     }
   }
 }

@@ -54,18 +54,16 @@ enum ErrorBits : uint32_t {
   kErrNonfinite = 32u,   // a particle's position was not finite or not in a cell
 };
 
-// Per-tile partial sums of one step, combined over the tiles of a species in a fixed
-// order by k_birth_scan (so the totals do not depend on the order tiles finish in).
+// Wall events of one tile in one step (written only by the tiles that have any, which
+// mark themselves in the species' event bitmap), combined in tile order by k_birth_scan
+// (so the totals do not depend on the order tiles finish in).
 struct TileStats {
-  double ke;          // sum of (v_x^2(n-1/2) + v_x^2(n+1/2)) / 2 + v_y^2 + v_z^2 (energy steps)
-  double mom;         // sum of v_x(n+1/2) (energy steps)
   double abs_e[2];    // energy of the particles absorbed at each wall [eV]
   uint32_t abs_n[2];  // particles absorbed at each wall
   uint32_t emit[2];   // secondary electrons emitted at each wall (ion species)
   uint32_t refl[2];   // electrons reflected at each wall (electron species)
-  uint32_t pushed;    // particles pushed
-  uint32_t alive;     // particles inside the box after the push (and the walls)
 };
+
 
 // Per-discharge results of the last step, normalised units (energy Q^2 dx / (eps0 A),
 // charge Q / A, potential Q dx / (eps0 A)).
@@ -141,7 +139,11 @@ struct SpeciesDev {
   unsigned long long GM* emitted;    // [2] secondary electrons emitted per wall (ions)
   unsigned long long GM* reflected;  // [2] electrons reflected per wall (electrons)
   unsigned long long GM* psteps;     // [1] particles stepped, summed over steps
-  TileStats GM* tstats;              // [n_tiles + n_tail] this step's per-tile sums
+  TileStats GM* tstats;              // [n_tiles + n_tail] this step's wall events per tile
+  uint32_t GM* ev_bits;              // [(n_tiles + n_tail + 31) / 32] tiles with wall events
+  uint2 GM* tcount;                  // [n_tiles + n_tail] particles pushed, alive per tile
+  double GM* tke;                    // [2 (n_tiles + n_tail)] kinetic energy, momentum sums
+                                     // per tile (energy steps)
   // fixed-point deposit: one = 2^dep_shift, inv = 2^-dep_shift
   unsigned long long dep_one;
   double dep_scale, dep_inv;
