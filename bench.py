@@ -141,11 +141,12 @@ def run_path(fs, torch, wls, precision, steps, warmup, tuning=None, cap_factor=1
     return out
 
 
-def _averages(fs, torch, wl, precision, steps, tuning=None, state=None, keep_state=False):
+def _averages(fs, torch, wl, precision, steps, tuning=None, state=None, keep_state=False,
+              cap_factor=1.5):
     """Time-averaged n_e, n_i, Phi (over the workload's averaging window) and the EEDF
     histogram after `steps` graph-replayed steps from the seeded load (or from `state`)."""
     import numpy as np
-    sim = fs.Simulation(wl, precision, tuning=tuning)
+    sim = fs.Simulation(wl, precision, tuning=tuning, cap_factor=cap_factor)
     if state is not None:
         sim.set_state(state)
     sim.set_graph(graph_length(steps))
@@ -258,14 +259,21 @@ def density_gate(fs, torch, workloads, steps, seeds):
                     "its stderr"}
 
 
-def oracle_averages(wl, steps):
+def oracle_averages(wl, steps, progress=None, cap_factor=1.5):
     """The FP64 oracle's time averages over the workload's window (same keys as
-    _averages), run on the host."""
+    _averages), run on the host (in pieces of 1000 steps, each reported to `progress`)."""
     import numpy as np
     import oracle
-    orc = oracle.Oracle(wl)
+    orc = oracle.Oracle(wl, cap_e=int(wl["n_e0"] * cap_factor) + 1024,
+                        cap_i=int(wl["n_i0"] * cap_factor) + 1024)
     orc.load()
-    orc.step(steps)
+    done = 0
+    while done < steps:
+        k = min(1000, steps - done)
+        orc.step(k)
+        done += k
+        if progress:
+            progress("oracle %d/%d steps" % (done, steps))
     t = orc.tallies()
     c = orc.consts()
     n = max(int(t.acc_count), 1)
@@ -293,7 +301,8 @@ def rf_gate(fs, torch, workloads, steps):
     seed1 = _averages(fs, torch, workloads.rf_c2(steps=steps, avg_start=max(0, steps - 400),
                                                  seed=1, sort_mode=SORT), "fp64", steps)
     t0 = time.perf_counter()
-    orc = oracle_averages(wl, steps)
+    orc = oracle_averages(wl, steps, progress=lambda m: print("bench: rf gate: " + m,
+                                                             file=sys.stderr, flush=True))
     return {"workload": "bounded RF discharge 2e5 + 2e5, %d steps, averages over the last "
                         "400" % steps,
             "fp64_vs_oracle": rel_l2(g64, orc), "fp32_offset_vs_fp64": rel_l2(g32, g64),
@@ -305,22 +314,38 @@ def long_run_study(fs, torch, workloads, steps, sub_steps):
     """The long run: FP32 against FP64 at full size (8192 cells, 3.2e7 + 3.2e7) over
     `steps` steps, and the FP64 GPU path against the oracle at the 1e5-per-species
     subsample over `sub_steps` steps, with the seed + 1 floors."""
+    def log(m):
+        print("bench: long-run study: " + m, file=sys.stderr, flush=True)
+
     half = steps // 2
     wl = workloads.long_c5(avg_start=half, sort_mode=SORT)
-    r64 = _averages(fs, torch, wl, "fp64", steps)
-    r32 = _averages(fs, torch, wl, "fp32_offset", steps)
+    # the discharge ionises its way up from the load: room for twice the load (the most
+    # the library allows at 3.2e7 per species: capacities stay below 2^26)
+    cf = 2.0
+    log("full size, FP64")
+    r64 = _averages(fs, torch, wl, "fp64", steps, cap_factor=cf)
+    log("full size, FP32 cell+offset")
+    r32 = _averages(fs, torch, wl, "fp32_offset", steps, cap_factor=cf)
+    log("full size, FP64, seed + 1")
     s1 = _averages(fs, torch, workloads.long_c5(avg_start=half, seed=1, sort_mode=SORT), "fp64",
-                   steps)
+                   steps, cap_factor=cf)
     sub = workloads.long_c5(n_e0=100_000, n_i0=100_000, avg_start=sub_steps // 2,
                             sort_mode=SORT)
-    g = _averages(fs, torch, sub, "fp64", sub_steps)
-    g1 = _averages(fs, torch, dict(sub, seed=1), "fp64", sub_steps)
+    log("subsample, FP64, seeds 0..4")
+    g = _averages(fs, torch, sub, "fp64", sub_steps, cap_factor=cf)
+    others = [_averages(fs, torch, dict(sub, seed=k), "fp64", sub_steps, cap_factor=cf)
+              for k in range(1, 5)]
+    g1 = others[0]
+    spread = [rel_l2(o_, g) for o_ in others]
+    log("subsample, oracle on the host")
     t0 = time.perf_counter()
-    o = oracle_averages(sub, sub_steps)
+    o = oracle_averages(sub, sub_steps, progress=log, cap_factor=cf)
     return {"full_size": {"steps": steps, "fp32_offset_vs_fp64": rel_l2(r32, r64),
                           "floor_fp64_seed_plus_1": rel_l2(s1, r64)},
             "subsample_1e5": {"steps": sub_steps, "fp64_vs_oracle": rel_l2(g, o),
                               "floor_fp64_seed_plus_1": rel_l2(g1, g),
+                              "floor_fp64_seeds_1_to_4": {
+                                  k: sorted(x[k] for x in spread) for k in QUANT},
                               "oracle_seconds": time.perf_counter() - t0}}
 
 
@@ -496,7 +521,7 @@ def main():
         # the paper's in-place fine sort against its sorting-cell size (N_gc = G + 1 grid
         # points per sorting cell, the paper's study of cycle time against N_gc)
         fine = {}
-        for g in (1, 2, 4, 8, 16):
+        for g in (1, 2, 4, 8):
             log("paper's fine sort, sorting cells of %d grid cells, FP32" % g)
             r = run_path(fs, torch, workloads.large_c3(sort_mode="fine",
                                                        grid_points_per_sort_cell=g + 1),

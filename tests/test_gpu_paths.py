@@ -325,3 +325,66 @@ def test_edge_states_one_step(fspic, oracle_mod, case, precision):
     else:
         compare_fp64(sim, orc, case, gbase=gb)
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+@pytest.mark.parametrize("case", sorted(EDGE_STATES))
+def test_edge_states_lagged_sort(fspic, oracle_mod, case, precision):
+    """The degenerate states under the lagged sort, two steps against the oracle: in the
+    second step the keys are the cells the first step left the particles in, so in the
+    all-far case every fast electron goes through the far list."""
+    from test_gpu_parity import compare_fp32, oracle_tallies
+    e = EDGE_STATES[case]
+    wl = workloads.periodic_c1(sort_mode="lag")
+    print("edge state, lagged sort", case, precision, flush=True)
+    st = workloads.synthetic_state(wl["n_cells"], e["n"], precision, seed=43,
+                                   vth=e.get("vth", (2.0, 0.02)), fast=e.get("fast", (0, 0)),
+                                   cells=e.get("cells"))
+    fp32 = precision == "fp32_offset"
+    sim = fspic.Simulation(wl, precision, tuning={"far_capacity": 8192})
+    sim.set_state(st)
+    orc = oracle_from_state(oracle_mod, wl, st, fp32)
+    sim.step(1)
+    orc.step(1)
+    st1 = sim.get_state()
+    gb, ob = tallies_of(sim.diagnostics()), oracle_tallies(orc.tallies())
+    sim.step(1)
+    orc.step(1)
+    if fp32:
+        compare_fp32(sim, orc, st1, case, gbase=gb, obase=ob)
+    else:
+        compare_fp64(sim, orc, case, gbase=gb, obase=ob)
+    sim.close()
+
+
+@pytest.mark.parametrize("sort", ["counting", "lag"])
+def test_full_size_batched_scan_sampled(fspic, oracle_mod, sort):
+    """The batched scan at full size (256 discharges, 2.9e8 particles at load) in one
+    simulation, in the FP32 layout and capacity the benchmark times: after 3 steps from the
+    loads, three discharges (the fewest particles, the median, the most) are set to seeded
+    states, and one more step of the whole batch is compared with the oracle for those
+    three, particle by particle, at the FP32 bar (one flipped channel decision allowed, as
+    for the large discharge)."""
+    from test_gpu_parity import compare_fp32, oracle_from_state, tallies_of
+    wls = [dict(w, sort_mode=sort) for w in workloads.batched_c4()]
+    sizes = np.array([w["n_e0"] for w in wls])
+    order = np.argsort(sizes, kind="stable")
+    picked = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    print("batched full size", sort, picked, [int(sizes[d]) for d in picked], flush=True)
+    sim = fspic.Simulation(wls, "fp32_offset", cap_factor=4.0)
+    sim.step(3)
+    states, orcs, gbs = {}, {}, {}
+    for d in picked:
+        wl = wls[d]
+        st = workloads.synthetic_state(wl["n_cells"], (wl["n_e0"], wl["n_i0"]), "fp32_offset",
+                                       seed=300 + d, vth=(1.5, 0.02), tail=(100, 100), step=3)
+        sim.set_state(st, d)
+        states[d] = st
+        orcs[d] = oracle_from_state(oracle_mod, wl, st, True)
+        gbs[d] = tallies_of(sim.diagnostics(d))
+    sim.step(1)
+    for d in picked:
+        orcs[d].step(1)
+        compare_fp32(sim, orcs[d], states[d], "batched full %d" % d, gbase=gbs[d], coll_slack=1,
+                     d=d)
+    sim.close()
