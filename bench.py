@@ -2,16 +2,21 @@
 
 Prints ONE JSON line.  The headline `value` is particle-steps/s of the FP32 cell + offset
 path on the large single discharge (4096 cells, 1e7 electrons + 1e7 ions, 5 Pa Ar-like
-gas, 300 V at 13.56 MHz, sort every step), inputs resident in HBM, the K timed steps
+gas, 300 V at 13.56 MHz, sorted by cell every step with the lagged counting sort (--sort
+counting: keyed on the post-push cell)), inputs resident in HBM, the K timed steps
 (steps W+1 .. W+K after the load, named in config.window) replayed from a captured HIP
 graph of a divisor of K steps and timed with HIP events on the library's stream.  The
 same W + K steps are then run again from the same seeded load with eager launches, every
 kernel bracketed by HIP events recorded by its own launch: the per-kernel durations of
 the K timed steps give the roofline of the dominant kernel (k_main).  The runs are bit
 for bit deterministic, so both time the same work.  Under "paths": the FP64 path, the
-unsorted variant and the long-run discharge (8192 cells, 3.2e7 + 3.2e7), each from its
-load, and the batched 256-discharge scan against the same discharges run one at a time.
-The oracle's CPU speed on bounded samples of the workloads comes alongside.
+other sort, the unsorted variant, the paper's in-place fine sort over sorting-cell sizes,
+the long-run discharge (8192 cells, 3.2e7 + 3.2e7), each from its load, and the batched
+256-discharge scan against the same discharges run one at a time.  The density gate
+(FP32 against FP64 on the large discharge, with controls and a paired-seed ensemble) and
+the bounded RF discharge against the oracle come alongside, and the oracle's CPU speed
+on bounded samples of the workloads.  --long-run-study adds the long run's precision
+study (minutes).
 
 `python bench.py --skip-paths --skip-cpu --gate-steps 0` runs only the two headline runs;
 that is the command whose rocprofv3 kernel statistics are kept beside the code.
