@@ -339,14 +339,12 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
     for (int c = 0; c < pl->sp[i].n_cells; c += kScanCells)
       pl->cell_table.push_back(make_int2(i, c));
   }
-  // MCC work: each electron tile alone (a few thousand candidates); the ion tiles' short
-  // lists kIonGroup tiles at a time when there are many of them (measured: the ion
-  // workgroups of one large discharge run for free beside the long electron ones, while
-  // the tens of thousands of a batch pay for their count); electron work first, the long
-  // workgroups starting early
-  int ion_tiles = 0;
-  for (int i = 1; i < 2 * n; i += 2) ion_tiles += pl->sp[i].n_tiles + pl->sp[i].n_tail;
-  const int ion_group = ion_tiles > kIonGroupAbove ? kIonGroup : 1;
+  // MCC work: each electron tile alone (a few thousand candidates, eight waves); the ion
+  // tiles' short lists kIonGroup tiles at a time, so that the ion workgroups, which pay
+  // the collision path's long dependent chain once per pass however few lanes they have,
+  // are few and take few of the CU slots the long electron workgroups need; electron work
+  // first, the long workgroups starting early
+  const int ion_group = kIonGroup;
   pl->collide_table.clear();
   for (int pass = 0; pass < 2; ++pass)
     for (int i = pass; i < 2 * n; i += 2) {

@@ -97,6 +97,12 @@ enum { XS_NONE = 0, XS_CONST_E_ELASTIC = 1, XS_AR_LIKE = 2 };
 constexpr double kExcEv = 11.5;
 constexpr double kIonEv = 15.8;
 
+// Each of the model's fractions is evaluated over one common denominator: the same
+// functions with one division instead of two or three, which round differently from the
+// nested form by a few units in the last place.
+//   elastic     3e-19 (x + 0.05) / (1 + x^2), x = eps / 12  =  3.6e-18 (eps + 0.6) / (144 + eps^2)
+//   excitation  2e-20 2u / (1 + u^2), u = (eps - 11.5) / 20  =  8e-19 a / (400 + a^2)
+//   ionisation  3e-20 2u / (1 + u^2), u = (eps - 15.8) / 60  =  3.6e-18 a / (3600 + a^2)
 __device__ __forceinline__ void xsec_electron(int model, double eps, double sc, double& el,
                                               double& ex, double& iz) {
   el = ex = iz = 0.0;
@@ -105,23 +111,27 @@ __device__ __forceinline__ void xsec_electron(int model, double eps, double sc, 
     return;
   }
   if (model != XS_AR_LIKE) return;
-  const double xe = eps / 12.0;
-  el = 3e-19 * (xe + 0.05) / (1.0 + xe * xe);
+  el = 3.6e-18 * (eps + 0.6) / (144.0 + eps * eps);
   if (eps > kExcEv) {
-    const double u = (eps - kExcEv) / 20.0;
-    ex = 2e-20 * (2.0 * u) / (1.0 + u * u);
+    const double a = eps - kExcEv;
+    ex = 8e-19 * a / (400.0 + a * a);
   }
   if (eps > kIonEv) {
-    const double u = (eps - kIonEv) / 60.0;
-    iz = 3e-20 * (2.0 * u) / (1.0 + u * u);
+    const double a = eps - kIonEv;
+    iz = 3.6e-18 * a / (3600.0 + a * a);
   }
 }
 
+//   isotropic       2e-19 (1 + 2 / (1 + eps)) / (1 + eps / 100)
+//                   =  2e-17 (3 + eps) / ((1 + eps) (100 + eps))
+//   charge exchange 3e-19 (1 + 1 / (1 + eps)) / (1 + eps / 1000)
+//                   =  3e-16 (2 + eps) / ((1 + eps) (1000 + eps))
 __device__ __forceinline__ void xsec_ion(int model, double eps, double& is, double& cx) {
   is = cx = 0.0;
   if (model != XS_AR_LIKE) return;
-  is = 2e-19 * (1.0 + 2.0 / (1.0 + eps)) / (1.0 + eps / 100.0);
-  cx = 3e-19 * (1.0 + 1.0 / (1.0 + eps)) / (1.0 + eps / 1000.0);
+  const double e1 = 1.0 + eps;
+  is = 2e-17 * (3.0 + eps) / (e1 * (100.0 + eps));
+  cx = 3e-16 * (2.0 + eps) / (e1 * (1000.0 + eps));
 }
 
 // ------------------------------------------------------------------------------------

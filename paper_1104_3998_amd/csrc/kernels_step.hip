@@ -98,22 +98,25 @@ __device__ __forceinline__ uint32_t real_off<P64>(const RecPtr& f, uint32_t i) {
   return f.boff8 + i * 8u;
 }
 
-// One MCC candidate record: output slot, id, post-push cell, position word and velocity.
-// FP32: two 16-byte halves (slot, id, cell, offset bits) (vx, vy, vz, -); FP64: three
-// (slot, id, cell, -) (x, vx) (vy, vz).
+// One MCC candidate record: output slot, id, words 1 and 2 of the particle's Philox block
+// 0 (the collision draw; word 0 made it a candidate), post-push position word and
+// velocity.  FP32: two 16-byte halves (slot, id, w1, w2) (vx, vy, vz, offset bits); FP64:
+// three (slot, id, w1, w2) (x, vx) (vy, vz).  The cell is the one of the record at the
+// slot (FP32), or floor(x) (FP64).
 template <class P>
 __device__ __forceinline__ void cand_store(void GM* base, uint32_t e, uint32_t dst,
-                                           uint32_t id, int d, typename Part0<P>::real pos,
+                                           uint32_t id, uint2 w12,
+                                           typename Part0<P>::real pos,
                                            typename Part0<P>::real vx,
                                            typename Part0<P>::real vy,
                                            typename Part0<P>::real vz) {
   if constexpr (std::is_same<P, P32>::value) {
     const uint32_t o = e * 32u;
-    sto<uint4>(base, o, make_uint4(dst, id, static_cast<uint32_t>(d), __float_as_uint(pos)));
-    sto<float4>(base, o + 16u, make_float4(vx, vy, vz, 0.0f));
+    sto<uint4>(base, o, make_uint4(dst, id, w12.x, w12.y));
+    sto<float4>(base, o + 16u, make_float4(vx, vy, vz, pos));
   } else {
     const uint32_t o = e * 48u;
-    sto<uint4>(base, o, make_uint4(dst, id, static_cast<uint32_t>(d), 0u));
+    sto<uint4>(base, o, make_uint4(dst, id, w12.x, w12.y));
     sto<double2>(base, o + 16u, make_double2(pos, vx));
     sto<double2>(base, o + 32u, make_double2(vy, vz));
   }
@@ -127,7 +130,7 @@ __device__ __forceinline__ uint4 cand_load(const void GM* base, uint32_t e,
     const uint32_t o = e * 32u;
     const uint4 a = ldo<uint4>(base, o);
     const float4 b = ldo<float4>(base, o + 16u);
-    pos = __uint_as_float(a.w);
+    pos = b.w;
     v[0] = b.x;
     v[1] = b.y;
     v[2] = b.z;
@@ -1458,6 +1461,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   // Push, walls (reflection, absorption, emission), EEDF, energy sums and the
   // null-collision test: common to both kinds of tile.
   // ek: the lagged sort's window slot of the record's present cell (cell tiles only)
+  uint2 cand_w12 = make_uint2(0u, 0u);  // words 1, 2 of the last tested particle's block 0
   auto push_and_test = [&](auto tail_tag, auto rev_tag, const Part<P>& q, bool valid, int& d,
                            real& pos, real& vxn, bool& cand, int ek) {
     constexpr bool kTail = decltype(tail_tag)::value;
@@ -1525,7 +1529,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     n_alive += static_cast<uint32_t>(__popcll(__ballot(st == 0)));
     if (st == 3) atomicOr(&sh.err, kErrNonfinite);
     cand = false;
-    if (st == 0 && s.t0 != 0u) cand = philox(q.id, step32, 0u, 0u, s.key0, s.key1).x < s.t0;
+    if (st == 0 && s.t0 != 0u) {
+      const uint4 b0 = philox(q.id, step32, 0u, 0u, s.key0, s.key1);
+      cand = b0.x < s.t0;
+      cand_w12 = make_uint2(b0.y, b0.z);
+    }
     return st;
   };
   // A candidate's entry (input order within the wave's piece) for k_collide; lanes that
@@ -1545,13 +1553,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       else
         e = wr.lo + n_cand + static_cast<uint32_t>(__popcll(cm & lt));
     }
-    cand_store<P>(s.cand, defer ? sink : e, dst, q.id, d, pos, vxn, q.vy, q.vz);
+    cand_store<P>(s.cand, defer ? sink : e, dst, q.id, cand_w12, pos, vxn, q.vy, q.vz);
     n_cand += static_cast<uint32_t>(__popcll(cm));
     return e;
   };
-  auto write_candidate = [&](uint32_t e, uint32_t dst, uint32_t id, int d, real pos, real vx,
+  // (a deferred candidate is rare: its draw words are computed again)
+  auto write_candidate = [&](uint32_t e, uint32_t dst, uint32_t id, real pos, real vx,
                              real vy, real vz) {
-    cand_store<P>(s.cand, e, dst, id, d, pos, vx, vy, vz);
+    const uint4 b0 = philox(id, step32, 0u, 0u, s.key0, s.key1);
+    cand_store<P>(s.cand, e, dst, id, make_uint2(b0.y, b0.z), pos, vx, vy, vz);
   };
 
   if (r.fine) {
@@ -1613,7 +1623,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           store_record<P>(out, dst, d, pos, vx, vy, vz, f[kQid]);
           if (!kLag) far_deposit<P>(s, d, pos);  // lagged: deposited in the loop
         }
-        if (f[kQid + 1] != kNoDest) write_candidate(f[kQid + 1], dst, f[kQid], d, pos, vx, vy, vz);
+        if (f[kQid + 1] != kNoDest) write_candidate(f[kQid + 1], dst, f[kQid], pos, vx, vy, vz);
       }
       qn = 0;
     };
@@ -1863,20 +1873,22 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ====================================================================================
 // k_collide: modified null-collision MCC (Sec. 3.8, eq. null_collision) of the candidates
 // k_main found (word 0 of the particle's Philox block 0 below floor(P0 2^32)).  A
-// workgroup takes a part of the candidates in input order (the tiles' waves' lists one
-// after the other), 256 at a time, so the collision path runs on full waves:
-// * an electron tile's list (a few thousand candidates) by one workgroup (splitting it
-//   over several was measured slower);
-// * the ion tiles' lists (a handful of candidates each) up to kIonGroup tiles at a time
-//   when there are many: every workgroup pays the collision path's long dependent chain
-//   once per pass, however few lanes it has.
-// k_main stored each candidate's post-push state beside its sorted slot; the
-// post-collision velocity is written to that slot.  Births (electron ionization) are
-// staged in the order of their parents (= input order); k_finalize appends and deposits
-// them.
+// workgroup of kCollideWG threads takes a part of the candidates in input order (the
+// tiles' waves' lists one after the other), kCollideWG at a time, so the collision path
+// runs on full waves:
+// * an electron tile's list (a few thousand candidates) by one workgroup of eight waves:
+//   the pass is a long dependent chain per lane, and eight waves per tile keep the SIMDs
+//   busier than four (splitting the list over workgroups instead would need the births'
+//   parent order across workgroups);
+// * the ion tiles' lists (a handful of candidates each) kIonGroup tiles at a time: every
+//   workgroup pays the collision path's chain once per pass, however few lanes it has.
+// k_main stored each candidate's post-push state and the rest of its Philox block 0
+// beside its sorted slot; the post-collision velocity is written to that slot.  Births
+// (electron ionization) are staged in the order of their parents (= input order);
+// k_finalize appends and deposits them.
 // ====================================================================================
 template <class P>
-__global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp) {
+__global__ __launch_bounds__(kCollideWG) void k_collide(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int4 cw = sim.collide_table[blockIdx.x];  // (species, first tile, tiles, 0)
@@ -1889,29 +1901,28 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   const TileRange r = tile_range(s, tile, p);
   // the (tile, wave) list segments of this workgroup's tiles, in input order
   constexpr int kSeg = kIonGroup * kWaves;
+  static_assert(kSeg <= kCollideWG, "one thread per list segment");
   __shared__ uint32_t sg_lo[kSeg], sg_pre[kSeg + 1];
-  __shared__ uint32_t bq[kWaves + 1];
+  __shared__ uint32_t bq[kCollideWG / 64 + 1];
   __shared__ uint32_t coll[3];
   const int tid = threadIdx.x;
-  if (tid < kSeg) {
-    const int g = tid / kWaves, w = tid - g * kWaves;
+  const int nseg = cw.z * kWaves;
+  {
     uint32_t nc = 0u, lo = 0u;
-    if (g < cw.z) {
+    if (tid < nseg) {
+      const int g = tid / kWaves, w = tid - g * kWaves;
       const TileRange rg = tile_range(s, tile + g, p);
       const WaveRange wr = piece_range(rg, w);  // w differs between the lanes
       nc = s.cand_cnt[(tile + g) * kWaves + w];
       lo = wave_reversed(rg, w) ? wr.hi - nc : wr.lo;  // see list_candidate in k_main
     }
-    // exclusive scan of the kSeg counts (lanes 0..kSeg-1 of wave 0)
-    uint32_t inc = nc;
-#pragma unroll
-    for (int o = 1; o < kSeg; o <<= 1) {
-      const uint32_t y = __shfl_up(inc, o, kSeg);
-      if (tid >= o) inc += y;
+    uint32_t tot;
+    const uint32_t pre = block_exclusive_scan<uint32_t>(nc, bq, tot);
+    if (tid < kSeg) {
+      sg_lo[tid] = lo;
+      sg_pre[tid] = pre;
     }
-    sg_lo[tid] = lo;
-    sg_pre[tid] = inc - nc;
-    if (tid == kSeg - 1) sg_pre[kSeg] = inc;
+    if (tid == 0) sg_pre[kSeg] = tot;
   }
   if (tid == 0) coll[0] = coll[1] = coll[2] = 0u;
   __syncthreads();
@@ -1927,7 +1938,7 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
   const RecPtr out = rec_buf(&sim.sp[cw.x], pq);
   const RecPtr stage_e = rec_stage(&sim.sp[cw.x], 0);
   const RecPtr stage_i = rec_stage(&sim.sp[cw.x], 1);
-  for (uint32_t b = 0; b < n; b += kWG) {
+  for (uint32_t b = 0; b < n; b += kCollideWG) {
     const uint32_t e = b + tid;
     bool born = false;
     uint32_t parent = 0u;
@@ -1935,21 +1946,17 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
     real pos = real(0);
     real vs[3] = {real(0), real(0), real(0)}, vi[3] = {real(0), real(0), real(0)};
     if (e < n) {
-      int w = 0;
-      for (int k = 1; k < cw.z * kWaves; ++k) w += e >= sg_pre[k] ? 1 : 0;
+      int w = 0;  // the last segment that starts at or before e (a non-empty one)
+#pragma unroll
+      for (int st = kSeg / 2; st >= 1; st >>= 1)
+        if (w + st < nseg && sg_pre[w + st] <= e) w += st;
       const uint32_t idx = sg_lo[w] + (e - sg_pre[w]);
       real v[3] = {real(0), real(0), real(0)};
       const uint4 c = idx < s.cap ? cand_load<P>(s.cand, idx, pos, v)
                                   : make_uint4(kNoDest, 0u, 0u, 0u);
       const uint32_t dst = c.x;
       if (dst != kNoDest && dst < s.cap) {
-        if constexpr (std::is_same<P, P32>::value) {
-          d = static_cast<int>(c.z);
-        } else {
-          d = static_cast<int>(floor(pos));
-        }
-        const uint4 b0 = philox(c.y, step32, 0u, 0u, s.key0, s.key1);
-        const int ch = collide<P>(s, c.y, step32, b0.y, b0.z, v, vs, vi);
+        const int ch = collide<P>(s, c.y, step32, c.z, c.w, v, vs, vi);
         if (ch > 0) {
           atomicAdd(&coll[ch - 1], 1u);
           const uint32_t o = real_off<P>(out, dst);
@@ -1958,6 +1965,10 @@ __global__ __launch_bounds__(kWG) void k_collide(const SimDev* __restrict__ simp
           sto<real>(out.f[F_VZ], o, v[2]);
           born = s.sp == 0 && ch == 3;
           parent = c.y;
+          if (born) {  // the births start at the parent's position
+            if constexpr (std::is_same<P, P32>::value) d = ldo<int>(out.f[F32_CELL], out.boff4 + dst * 4u);
+            else d = static_cast<int>(floor(pos));
+          }
         }
       }
     }
@@ -2475,8 +2486,8 @@ void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hip
                     hipEvent_t e1) {
   const dim3 grid(li.n_collide_wgs);
   hipEvent_t e1c = li.emission ? static_cast<hipEvent_t>(nullptr) : e1;
-  if (li.fp32) launch(k_collide<P32>, grid, dim3(kWG), st, e0, e1c, sim);
-  else launch(k_collide<P64>, grid, dim3(kWG), st, e0, e1c, sim);
+  if (li.fp32) launch(k_collide<P32>, grid, dim3(kCollideWG), st, e0, e1c, sim);
+  else launch(k_collide<P64>, grid, dim3(kCollideWG), st, e0, e1c, sim);
   if (li.emission) {
     const dim3 eg((li.total_tiles + kWaves - 1) / kWaves);
     if (li.fp32) launch(k_emit<P32>, eg, dim3(kWG), st, static_cast<hipEvent_t>(nullptr), e1, sim);
