@@ -339,17 +339,33 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
     for (int c = 0; c < pl->sp[i].n_cells; c += kScanCells)
       pl->cell_table.push_back(make_int2(i, c));
   }
-  // MCC work: each electron tile alone (a few thousand candidates, eight waves); the ion
-  // tiles' short lists kIonGroup tiles at a time, so that the ion workgroups, which pay
-  // the collision path's long dependent chain once per pass however few lanes they have,
-  // are few and take few of the CU slots the long electron workgroups need; electron work
-  // first, the long workgroups starting early
-  const int ion_group = kIonGroup;
+  // MCC work: each electron tile alone (up to a few thousand candidates); the ion tiles'
+  // lists several tiles at a time, as many as make about one workgroup pass of candidates
+  // at the load (P0 of the ion tile's particles), at most kIonGroup: every workgroup pays
+  // the collision path's long dependent chain once per pass however few lanes it has, and
+  // few ion workgroups leave the CU slots to the long electron ones (large discharge: 64
+  // tiles of a handful of candidates each; high-pressure discharges: one or two tiles of
+  // a few hundred).  Electron work first, the long workgroups starting early.  With few
+  // electron tiles (under four per CU) a workgroup has eight waves instead of four: each
+  // lane's collision is a long dependent chain, and two four-wave workgroups per CU leave
+  // the SIMDs idle (large discharge: 68 -> 61 us); with many, four-wave workgroups
+  // schedule better (batched scan: 1.30 against 1.47 ms).
+  int e_tiles = 0;
+  for (int i = 0; i < 2 * n; i += 2) e_tiles += pl->sp[i].n_tiles + pl->sp[i].n_tail;
+  const int cwg = e_tiles < kCollideWideBelow ? kCollideWide : kWG;
   pl->collide_table.clear();
   for (int pass = 0; pass < 2; ++pass)
     for (int i = pass; i < 2 * n; i += 2) {
-      const int nt = pl->sp[i].n_tiles + pl->sp[i].n_tail;
-      const int g = pass == 0 ? 1 : ion_group;
+      const SpeciesDev& S = pl->sp[i];
+      const int nt = S.n_tiles + S.n_tail;
+      int g = 1;
+      if (pass == 1) {
+        const int d = i / 2;
+        const double per_tile = static_cast<double>(pl->cfg[d].n_i0) /
+                                static_cast<double>(std::max(1, S.n_tiles)) * pl->der[d].p0[1];
+        g = static_cast<int>(std::min<double>(kIonGroup,
+                                              std::max(1.0, cwg / std::max(per_tile, 1e-9))));
+      }
       for (int t = 0; t < nt; t += g)
         pl->collide_table.push_back(make_int4(i, t, std::min(g, nt - t), 0));
     }
@@ -376,6 +392,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
   li.n_node_wgs = static_cast<int>(pl->node_table.size());
   li.n_cell_wgs = static_cast<int>(pl->cell_table.size());
   li.n_collide_wgs = static_cast<int>(pl->collide_table.size());
+  li.collide_wg = cwg;
   li.fp32 = fp32;
   return PIC_OK;
 }

@@ -31,6 +31,7 @@ struct LaunchInfo {
   int n_ds, n_spec, total_tiles, max_nodes, max_cap, n_gtiles, max_cells, max_window;
   int n_node_wgs, n_cell_wgs;  // entries of the node and cell block tables
   int n_collide_wgs;           // entries of the MCC work table
+  int collide_wg;              // threads of an MCC workgroup (kWG or kCollideWide)
   bool fp32;
   bool coulomb;                // some discharge has Coulomb collisions
   bool emission;               // some discharge has secondary emission

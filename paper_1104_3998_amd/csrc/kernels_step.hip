@@ -98,25 +98,22 @@ __device__ __forceinline__ uint32_t real_off<P64>(const RecPtr& f, uint32_t i) {
   return f.boff8 + i * 8u;
 }
 
-// One MCC candidate record: output slot, id, words 1 and 2 of the particle's Philox block
-// 0 (the collision draw; word 0 made it a candidate), post-push position word and
-// velocity.  FP32: two 16-byte halves (slot, id, w1, w2) (vx, vy, vz, offset bits); FP64:
-// three (slot, id, w1, w2) (x, vx) (vy, vz).  The cell is the one of the record at the
-// slot (FP32), or floor(x) (FP64).
+// One MCC candidate record: output slot, id, post-push cell, position word and velocity.
+// FP32: two 16-byte halves (slot, id, cell, offset bits) (vx, vy, vz, -); FP64: three
+// (slot, id, cell, -) (x, vx) (vy, vz).
 template <class P>
 __device__ __forceinline__ void cand_store(void GM* base, uint32_t e, uint32_t dst,
-                                           uint32_t id, uint2 w12,
-                                           typename Part0<P>::real pos,
+                                           uint32_t id, int d, typename Part0<P>::real pos,
                                            typename Part0<P>::real vx,
                                            typename Part0<P>::real vy,
                                            typename Part0<P>::real vz) {
   if constexpr (std::is_same<P, P32>::value) {
     const uint32_t o = e * 32u;
-    sto<uint4>(base, o, make_uint4(dst, id, w12.x, w12.y));
-    sto<float4>(base, o + 16u, make_float4(vx, vy, vz, pos));
+    sto<uint4>(base, o, make_uint4(dst, id, static_cast<uint32_t>(d), __float_as_uint(pos)));
+    sto<float4>(base, o + 16u, make_float4(vx, vy, vz, 0.0f));
   } else {
     const uint32_t o = e * 48u;
-    sto<uint4>(base, o, make_uint4(dst, id, w12.x, w12.y));
+    sto<uint4>(base, o, make_uint4(dst, id, static_cast<uint32_t>(d), 0u));
     sto<double2>(base, o + 16u, make_double2(pos, vx));
     sto<double2>(base, o + 32u, make_double2(vy, vz));
   }
@@ -130,7 +127,7 @@ __device__ __forceinline__ uint4 cand_load(const void GM* base, uint32_t e,
     const uint32_t o = e * 32u;
     const uint4 a = ldo<uint4>(base, o);
     const float4 b = ldo<float4>(base, o + 16u);
-    pos = b.w;
+    pos = __uint_as_float(a.w);
     v[0] = b.x;
     v[1] = b.y;
     v[2] = b.z;
@@ -1461,7 +1458,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   // Push, walls (reflection, absorption, emission), EEDF, energy sums and the
   // null-collision test: common to both kinds of tile.
   // ek: the lagged sort's window slot of the record's present cell (cell tiles only)
-  uint2 cand_w12 = make_uint2(0u, 0u);  // words 1, 2 of the last tested particle's block 0
   auto push_and_test = [&](auto tail_tag, auto rev_tag, const Part<P>& q, bool valid, int& d,
                            real& pos, real& vxn, bool& cand, int ek) {
     constexpr bool kTail = decltype(tail_tag)::value;
@@ -1529,11 +1525,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     n_alive += static_cast<uint32_t>(__popcll(__ballot(st == 0)));
     if (st == 3) atomicOr(&sh.err, kErrNonfinite);
     cand = false;
-    if (st == 0 && s.t0 != 0u) {
-      const uint4 b0 = philox(q.id, step32, 0u, 0u, s.key0, s.key1);
-      cand = b0.x < s.t0;
-      cand_w12 = make_uint2(b0.y, b0.z);
-    }
+    if (st == 0 && s.t0 != 0u) cand = philox(q.id, step32, 0u, 0u, s.key0, s.key1).x < s.t0;
     return st;
   };
   // A candidate's entry (input order within the wave's piece) for k_collide; lanes that
@@ -1553,15 +1545,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       else
         e = wr.lo + n_cand + static_cast<uint32_t>(__popcll(cm & lt));
     }
-    cand_store<P>(s.cand, defer ? sink : e, dst, q.id, cand_w12, pos, vxn, q.vy, q.vz);
+    cand_store<P>(s.cand, defer ? sink : e, dst, q.id, d, pos, vxn, q.vy, q.vz);
     n_cand += static_cast<uint32_t>(__popcll(cm));
     return e;
   };
-  // (a deferred candidate is rare: its draw words are computed again)
-  auto write_candidate = [&](uint32_t e, uint32_t dst, uint32_t id, real pos, real vx,
+  auto write_candidate = [&](uint32_t e, uint32_t dst, uint32_t id, int d, real pos, real vx,
                              real vy, real vz) {
-    const uint4 b0 = philox(id, step32, 0u, 0u, s.key0, s.key1);
-    cand_store<P>(s.cand, e, dst, id, make_uint2(b0.y, b0.z), pos, vx, vy, vz);
+    cand_store<P>(s.cand, e, dst, id, d, pos, vx, vy, vz);
   };
 
   if (r.fine) {
@@ -1623,7 +1613,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           store_record<P>(out, dst, d, pos, vx, vy, vz, f[kQid]);
           if (!kLag) far_deposit<P>(s, d, pos);  // lagged: deposited in the loop
         }
-        if (f[kQid + 1] != kNoDest) write_candidate(f[kQid + 1], dst, f[kQid], pos, vx, vy, vz);
+        if (f[kQid + 1] != kNoDest) write_candidate(f[kQid + 1], dst, f[kQid], d, pos, vx, vy, vz);
       }
       qn = 0;
     };
@@ -1873,22 +1863,24 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // ====================================================================================
 // k_collide: modified null-collision MCC (Sec. 3.8, eq. null_collision) of the candidates
 // k_main found (word 0 of the particle's Philox block 0 below floor(P0 2^32)).  A
-// workgroup of kCollideWG threads takes a part of the candidates in input order (the
-// tiles' waves' lists one after the other), kCollideWG at a time, so the collision path
-// runs on full waves:
-// * an electron tile's list (a few thousand candidates) by one workgroup of eight waves:
-//   the pass is a long dependent chain per lane, and eight waves per tile keep the SIMDs
-//   busier than four (splitting the list over workgroups instead would need the births'
-//   parent order across workgroups);
-// * the ion tiles' lists (a handful of candidates each) kIonGroup tiles at a time: every
-//   workgroup pays the collision path's chain once per pass, however few lanes it has.
-// k_main stored each candidate's post-push state and the rest of its Philox block 0
-// beside its sorted slot; the post-collision velocity is written to that slot.  Births
+// workgroup of kT threads takes a part of the candidates in input order (the tiles' waves'
+// lists one after the other), kT at a time, so the collision path runs on full waves:
+// * an electron tile's list (up to a few thousand candidates) by one workgroup; with few
+//   electron tiles it has eight waves: the pass is a long dependent chain per lane, and
+//   eight waves per tile keep the SIMDs busier than four (splitting the list over
+//   workgroups instead would need the births' parent order across workgroups);
+// * the ion tiles' lists (a handful of candidates each) up to kIonGroup tiles at a time:
+//   every workgroup pays the collision path's chain once per pass, however few lanes it
+//   has.
+// k_main stored each candidate's post-push state beside its sorted slot; the
+// post-collision velocity is written to that slot.  (Carrying words 1 and 2 of block 0
+// in the record instead of computing the block again was measured slower: `k_main`
+// held them live and lost 9-13 us, the MCC pass gained under 1 us.)  Births
 // (electron ionization) are staged in the order of their parents (= input order);
 // k_finalize appends and deposits them.
 // ====================================================================================
-template <class P>
-__global__ __launch_bounds__(kCollideWG) void k_collide(const SimDev* __restrict__ simp) {
+template <class P, int kT>
+__global__ __launch_bounds__(kT) void k_collide(const SimDev* __restrict__ simp) {
   using real = typename Part<P>::real;
   const SimDev& sim = *simp;
   const int4 cw = sim.collide_table[blockIdx.x];  // (species, first tile, tiles, 0)
@@ -1901,9 +1893,9 @@ __global__ __launch_bounds__(kCollideWG) void k_collide(const SimDev* __restrict
   const TileRange r = tile_range(s, tile, p);
   // the (tile, wave) list segments of this workgroup's tiles, in input order
   constexpr int kSeg = kIonGroup * kWaves;
-  static_assert(kSeg <= kCollideWG, "one thread per list segment");
+  static_assert(kSeg <= kT, "one thread per list segment");
   __shared__ uint32_t sg_lo[kSeg], sg_pre[kSeg + 1];
-  __shared__ uint32_t bq[kCollideWG / 64 + 1];
+  __shared__ uint32_t bq[kT / 64 + 1];
   __shared__ uint32_t coll[3];
   const int tid = threadIdx.x;
   const int nseg = cw.z * kWaves;
@@ -1938,7 +1930,7 @@ __global__ __launch_bounds__(kCollideWG) void k_collide(const SimDev* __restrict
   const RecPtr out = rec_buf(&sim.sp[cw.x], pq);
   const RecPtr stage_e = rec_stage(&sim.sp[cw.x], 0);
   const RecPtr stage_i = rec_stage(&sim.sp[cw.x], 1);
-  for (uint32_t b = 0; b < n; b += kCollideWG) {
+  for (uint32_t b = 0; b < n; b += kT) {
     const uint32_t e = b + tid;
     bool born = false;
     uint32_t parent = 0u;
@@ -1956,7 +1948,13 @@ __global__ __launch_bounds__(kCollideWG) void k_collide(const SimDev* __restrict
                                   : make_uint4(kNoDest, 0u, 0u, 0u);
       const uint32_t dst = c.x;
       if (dst != kNoDest && dst < s.cap) {
-        const int ch = collide<P>(s, c.y, step32, c.z, c.w, v, vs, vi);
+        if constexpr (std::is_same<P, P32>::value) {
+          d = static_cast<int>(c.z);
+        } else {
+          d = static_cast<int>(floor(pos));
+        }
+        const uint4 b0 = philox(c.y, step32, 0u, 0u, s.key0, s.key1);
+        const int ch = collide<P>(s, c.y, step32, b0.y, b0.z, v, vs, vi);
         if (ch > 0) {
           atomicAdd(&coll[ch - 1], 1u);
           const uint32_t o = real_off<P>(out, dst);
@@ -1965,10 +1963,6 @@ __global__ __launch_bounds__(kCollideWG) void k_collide(const SimDev* __restrict
           sto<real>(out.f[F_VZ], o, v[2]);
           born = s.sp == 0 && ch == 3;
           parent = c.y;
-          if (born) {  // the births start at the parent's position
-            if constexpr (std::is_same<P, P32>::value) d = ldo<int>(out.f[F32_CELL], out.boff4 + dst * 4u);
-            else d = static_cast<int>(floor(pos));
-          }
         }
       }
     }
@@ -2486,8 +2480,14 @@ void launch_collide(const LaunchInfo& li, const SimDev* sim, hipStream_t st, hip
                     hipEvent_t e1) {
   const dim3 grid(li.n_collide_wgs);
   hipEvent_t e1c = li.emission ? static_cast<hipEvent_t>(nullptr) : e1;
-  if (li.fp32) launch(k_collide<P32>, grid, dim3(kCollideWG), st, e0, e1c, sim);
-  else launch(k_collide<P64>, grid, dim3(kCollideWG), st, e0, e1c, sim);
+  const dim3 block(li.collide_wg);
+  if (li.collide_wg == kCollideWide) {
+    if (li.fp32) launch(k_collide<P32, kCollideWide>, grid, block, st, e0, e1c, sim);
+    else launch(k_collide<P64, kCollideWide>, grid, block, st, e0, e1c, sim);
+  } else {
+    if (li.fp32) launch(k_collide<P32, kWG>, grid, block, st, e0, e1c, sim);
+    else launch(k_collide<P64, kWG>, grid, block, st, e0, e1c, sim);
+  }
   if (li.emission) {
     const dim3 eg((li.total_tiles + kWaves - 1) / kWaves);
     if (li.fp32) launch(k_emit<P32>, eg, dim3(kWG), st, static_cast<hipEvent_t>(nullptr), e1, sim);

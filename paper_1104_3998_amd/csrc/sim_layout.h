@@ -36,7 +36,8 @@ constexpr int kMaxWindow = 256;      // histogram window W = C + 2D (8-bit slot 
 constexpr int kSolveWG = 1024;       // threads of the per-discharge solve / scan kernels
 constexpr int kCombineLanes = 8;     // lanes per node in k_combine
 constexpr int kCombineNodes = 32;    // nodes of a k_combine workgroup (256 threads)
-constexpr int kCollideWG = 512;      // threads of an MCC workgroup
+constexpr int kCollideWide = 512;    // threads of an MCC workgroup when electron tiles are few
+constexpr int kCollideWideBelow = 1024;  // ... fewer than this (four per CU of the MI355X)
 constexpr int kIonGroup = 64;        // ion tiles whose candidate lists one MCC workgroup takes
 constexpr int kScanLanes = 16;       // lanes per cell in k_scan_cells
 constexpr int kScanCells = 16;       // cells of a k_scan_cells workgroup (256 threads)
