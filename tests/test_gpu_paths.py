@@ -268,6 +268,33 @@ def test_tile_geometry_does_not_change_results(fspic, precision):
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_offset"])
+def test_mcc_workgroup_width_does_not_change_results(fspic, precision):
+    """The MCC pass runs eight-wave workgroups when a simulation has few electron tiles and
+    four-wave ones when it has many (1024 or more), with the ion tiles grouped by their
+    expected candidates: 20 steps of a 2048-cell discharge with the default geometry (32
+    electron tiles) and with one cell per tile (2048) give the same state bit for bit and
+    the same integer tallies."""
+    wl = workloads.bounded(2048, 40000, 200.0, 30.0, steps=20, avg_start=10)
+    from paper_1104_3998_amd import autotune as at
+    (ce, de), (ci, di) = at.rule_geometry([wl], precision)[0]
+    assert (2048 + ce - 1) // ce < 1024
+    one = [{"cells_per_tile": (1, 1), "window": (de, max(di, 1))}]
+    print("rule C", ce, ci, "against one cell per tile", flush=True)
+    a = fspic.Simulation(wl, precision)
+    b = fspic.Simulation(wl, precision, tuning=one)
+    a.step(20)
+    b.step(20)
+    bitwise_equal_states(a.get_state(), b.get_state(), precision == "fp32_offset", "mcc width")
+    ga, gb = tallies_of(a.diagnostics()), tallies_of(b.diagnostics())
+    assert sum(ga[0]["coll"]) > 0 and sum(ga[1]["coll"]) > 0
+    for sp in (0, 1):
+        for k in ("coll", "absorbed", "births"):
+            assert ga[sp][k] == gb[sp][k], (sp, k)
+    a.close()
+    b.close()
+
+
 def test_autotune_and_cache(fspic, tmp_path):
     """The tuner times the rule and its scaled variants on a small batch, returns one
     tuning per discharge with a rate for the rule, and a second call with the same cache
