@@ -113,11 +113,11 @@ def test_batched_discharges_match_oracle_each(fspic, oracle_mod, sort):
 
 
 def test_grouped_ion_mcc_matches_oracle(fspic, oracle_mod):
-    """Five 2048-cell discharges at 100 Pa with one-cell ion tiles: 10320 ion tiles, more
-    than the 8192 above which the MCC pass takes four ion tiles' candidate lists (about
-    1000 ion candidates per discharge, P0 = 0.05) per workgroup.  One step from seeded
-    states with an unsorted births tail matches every discharge's oracle at the FP64 bar,
-    ion collisions included."""
+    """Five 2048-cell discharges at 100 Pa with one-cell ion tiles: 10320 ion tiles of
+    about 10 ions each (about 1000 ion candidates per discharge, P0 = 0.05), so the MCC
+    pass takes 64 ion tiles' candidate lists (256 list segments) per workgroup.  One step
+    from seeded states with an unsorted births tail matches every discharge's oracle at
+    the FP64 bar, ion collisions included."""
     wls = [workloads.bounded(2048, 20000, 300.0, 100.0, discharge=k, seed=k, steps=10)
            for k in range(5)]
     print("grouped ion MCC", flush=True)
