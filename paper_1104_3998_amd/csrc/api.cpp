@@ -176,28 +176,43 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       // the two buffers of a field are one allocation, buffer 1 a fixed distance above
       // buffer 0, so the kernels reach both from one base pointer
       const size_t st4 = align_up(4 * cap1, 256), st8 = align_up(8 * cap1, 256);
+      const size_t st16 = align_up(16 * cap1, 256);
       S.bstride4 = static_cast<uint32_t>(st4);
       S.bstride8 = static_cast<uint32_t>(st8);
+      S.bstride16 = static_cast<uint32_t>(st16);
       for (int f = 0; f < 6; ++f) {
         if (!fp32 && f == 1) {
           S.fld[0][f] = S.fld[1][f] = nullptr;
           continue;
         }
+        if (fp32 && f >= F_VX) continue;  // the velocity records, below
         const size_t st = (fp32 || f == F_ID) ? st4 : st8;
         char* pair = cv.take<char>(2 * st);
         S.fld[0][f] = pair;
         S.fld[1][f] = pair ? pair + st : nullptr;
       }
+      if (fp32) {
+        char* pair = cv.take<char>(2 * st16);
+        for (int b = 0; b < 2; ++b)
+          for (int f = F_VX; f <= F_ID; ++f)
+            S.fld[b][f] = pair ? pair + b * st16 + 4 * (f - F_VX) : nullptr;
+      }
+      // FP32 velocity records of n elements: vx, vy, vz (and id) pointers into one array
+      auto vel_records = [&](void** fl, size_t n) {
+        char* v = cv.take<char>(16 * n);
+        for (int f = F_VX; f <= F_ID; ++f) fl[f] = v ? v + 4 * (f - F_VX) : nullptr;
+      };
       if (s == 0) {
         for (int b = 0; b < 2; ++b) {
           if (fp32) {
             S.stage[b][F32_CELL] = cv.take<int>(cap);
             S.stage[b][F32_OFF] = cv.take<float>(cap);
+            vel_records(S.stage[b], cap);
           } else {
             S.stage[b][F64_X] = cv.take<double>(cap);
             S.stage[b][1] = nullptr;
+            for (int f = F_VX; f <= F_VZ; ++f) S.stage[b][f] = cv.take<char>(rs * cap);
           }
-          for (int f = F_VX; f <= F_VZ; ++f) S.stage[b][f] = cv.take<char>(rs * cap);
           S.stage[b][F_ID] = nullptr;
         }
       }
@@ -207,8 +222,10 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       if (c.sort_mode == PIC_SORT_FINE) {
         for (int f = 0; f < 6; ++f) {
           if (!fp32 && f == 1) continue;
+          if (fp32 && f >= F_VX) continue;
           S.fine[f] = cv.take<char>(((fp32 || f == F_ID) ? 4 : 8) * cap1);
         }
+        if (fp32) vel_records(S.fine, cap1);
         S.fcnt = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles));
         S.flv = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles));
         if (s == 0) {
@@ -268,10 +285,12 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
         if (fp32) {
           S.em_stage[F32_CELL] = cv.take<int>(cap);
           S.em_stage[F32_OFF] = cv.take<float>(cap);
+          vel_records(S.em_stage, cap);
+          S.em_stage[F_ID] = nullptr;
         } else {
           S.em_stage[F64_X] = cv.take<double>(cap);
+          for (int f = F_VX; f <= F_VZ; ++f) S.em_stage[f] = cv.take<char>(rs * cap);
         }
-        for (int f = F_VX; f <= F_VZ; ++f) S.em_stage[f] = cv.take<char>(rs * cap);
         S.ab_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
         S.em_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
         S.em_lo = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
@@ -707,6 +726,21 @@ static int h2d(pic_sim* sim, T* dev, const T* host, size_t count) {
   return PIC_OK;
 }
 
+// FP32 velocity records (vx, vy, vz, id words) and the host's per-field arrays (any of
+// them may be null: not wanted).
+struct VelRec {
+  float vx, vy, vz;
+  uint32_t id;
+};
+static_assert(sizeof(VelRec) == 16, "16-byte velocity records");
+
+static void split_vel(const VelRec& r, size_t o, float* vx, float* vy, float* vz, uint32_t* id) {
+  if (vx) vx[o] = r.vx;
+  if (vy) vy[o] = r.vy;
+  if (vz) vz[o] = r.vz;
+  if (id) id[o] = r.id;
+}
+
 static uint64_t device_step(pic_sim* sim, int* rc) {
   unsigned long long st = 0;
   *rc = d2h(sim, &st, sim->pl.sim.step, 1);
@@ -903,9 +937,11 @@ static int fine_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, pic_
   if (fp32) {
     if ((rc = fine_gather(sim, S, f[F32_CELL], st->cell[s], cnt))) return rc;
     if ((rc = fine_gather(sim, S, f[F32_OFF], st->off[s], cnt))) return rc;
-    if ((rc = fine_gather(sim, S, f[F_VX], st->vxf[s], cnt))) return rc;
-    if ((rc = fine_gather(sim, S, f[F_VY], st->vyf[s], cnt))) return rc;
-    if ((rc = fine_gather(sim, S, f[F_VZ], st->vzf[s], cnt))) return rc;
+    std::vector<VelRec> rec(static_cast<size_t>(n));
+    if ((rc = fine_gather(sim, S, f[F_VX], reinterpret_cast<VelRec*>(rec.data()), cnt))) return rc;
+    for (size_t i = 0; i < rec.size(); ++i)
+      split_vel(rec[i], i, st->vxf[s], st->vyf[s], st->vzf[s], st->id[s]);
+    return PIC_OK;
   } else {
     if ((rc = fine_gather(sim, S, f[F64_X], st->x[s], cnt))) return rc;
     if ((rc = fine_gather(sim, S, f[F_VX], st->vx[s], cnt))) return rc;
@@ -940,9 +976,13 @@ static int lag_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, int p
     for (uint32_t i = 0; i < nt; ++i) live[i] = cell[i] >= 0;
     if ((rc = lag_gather(sim, f[F32_CELL], st->cell[s], live))) return rc;
     if ((rc = lag_gather(sim, f[F32_OFF], st->off[s], live))) return rc;
-    if ((rc = lag_gather(sim, f[F_VX], st->vxf[s], live))) return rc;
-    if ((rc = lag_gather(sim, f[F_VY], st->vyf[s], live))) return rc;
-    if ((rc = lag_gather(sim, f[F_VZ], st->vzf[s], live))) return rc;
+    size_t n_live = 0;
+    for (char l : live) n_live += l ? 1 : 0;
+    std::vector<VelRec> rec(n_live);
+    if ((rc = lag_gather(sim, f[F_VX], rec.data(), live))) return rc;
+    for (size_t i = 0; i < rec.size(); ++i)
+      split_vel(rec[i], i, st->vxf[s], st->vyf[s], st->vzf[s], st->id[s]);
+    return PIC_OK;
   } else {
     std::vector<double> x(nt);
     if ((rc = d2h(sim, x.data(), static_cast<const double*>(f[F64_X]), nt))) return rc;
@@ -1001,16 +1041,19 @@ extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
     if (fp32) {
       if (st->cell[s] && (rc = d2h(sim, st->cell[s], static_cast<const int32_t*>(f[F32_CELL]), nt))) return rc;
       if (st->off[s] && (rc = d2h(sim, st->off[s], static_cast<const float*>(f[F32_OFF]), nt))) return rc;
-      if (st->vxf[s] && (rc = d2h(sim, st->vxf[s], static_cast<const float*>(f[F_VX]), nt))) return rc;
-      if (st->vyf[s] && (rc = d2h(sim, st->vyf[s], static_cast<const float*>(f[F_VY]), nt))) return rc;
-      if (st->vzf[s] && (rc = d2h(sim, st->vzf[s], static_cast<const float*>(f[F_VZ]), nt))) return rc;
+      if (st->vxf[s] || st->vyf[s] || st->vzf[s] || st->id[s]) {
+        std::vector<VelRec> rec(nt);
+        if ((rc = d2h(sim, rec.data(), static_cast<const VelRec*>(f[F_VX]), nt))) return rc;
+        for (uint32_t i = 0; i < nt; ++i)
+          split_vel(rec[i], i, st->vxf[s], st->vyf[s], st->vzf[s], st->id[s]);
+      }
     } else {
       if (st->x[s] && (rc = d2h(sim, st->x[s], static_cast<const double*>(f[F64_X]), nt))) return rc;
       if (st->vx[s] && (rc = d2h(sim, st->vx[s], static_cast<const double*>(f[F_VX]), nt))) return rc;
       if (st->vy[s] && (rc = d2h(sim, st->vy[s], static_cast<const double*>(f[F_VY]), nt))) return rc;
       if (st->vz[s] && (rc = d2h(sim, st->vz[s], static_cast<const double*>(f[F_VZ]), nt))) return rc;
+      if (st->id[s] && (rc = d2h(sim, st->id[s], static_cast<const uint32_t*>(f[F_ID]), nt))) return rc;
     }
-    if (st->id[s] && (rc = d2h(sim, st->id[s], static_cast<const uint32_t*>(f[F_ID]), nt))) return rc;
     if (st->w[s] && (rc = d2h(sim, st->w[s], D.w[s], D.n_nodes))) return rc;
   }
   st->step = step;
@@ -1088,16 +1131,17 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
     if (fp32) {
       if ((rc = h2d(sim, static_cast<int32_t*>(f[F32_CELL]), st->cell[s], n))) return rc;
       if ((rc = h2d(sim, static_cast<float*>(f[F32_OFF]), st->off[s], n))) return rc;
-      if ((rc = h2d(sim, static_cast<float*>(f[F_VX]), st->vxf[s], n))) return rc;
-      if ((rc = h2d(sim, static_cast<float*>(f[F_VY]), st->vyf[s], n))) return rc;
-      if ((rc = h2d(sim, static_cast<float*>(f[F_VZ]), st->vzf[s], n))) return rc;
+      std::vector<VelRec> rec(n);
+      for (uint32_t i = 0; i < n; ++i)
+        rec[i] = VelRec{st->vxf[s][i], st->vyf[s][i], st->vzf[s][i], st->id[s][i]};
+      if ((rc = h2d(sim, static_cast<VelRec*>(f[F_VX]), rec.data(), n))) return rc;
     } else {
       if ((rc = h2d(sim, static_cast<double*>(f[F64_X]), st->x[s], n))) return rc;
       if ((rc = h2d(sim, static_cast<double*>(f[F_VX]), st->vx[s], n))) return rc;
       if ((rc = h2d(sim, static_cast<double*>(f[F_VY]), st->vy[s], n))) return rc;
       if ((rc = h2d(sim, static_cast<double*>(f[F_VZ]), st->vz[s], n))) return rc;
+      if ((rc = h2d(sim, static_cast<uint32_t*>(f[F_ID]), st->id[s], n))) return rc;
     }
-    if ((rc = h2d(sim, static_cast<uint32_t*>(f[F_ID]), st->id[s], n))) return rc;
     const uint32_t cnt[2] = {n, ns};
     const uint32_t no_holes[2] = {0u, 0u};
     if ((rc = h2d(sim, S.n_total + up, &cnt[0], 1))) return rc;

@@ -44,26 +44,37 @@ struct CReal<C64> {
   using type = double;
 };
 
+// FP32: vx, vy, vz are words 0-2 of the particle's 16-byte velocity record, the id word 3
 template <class P>
 __device__ __forceinline__ void load_v(const SpeciesDev& s, int buf, uint32_t i, double v[3]) {
   using real = typename CReal<P>::type;
-  for (int a = 0; a < 3; ++a)
-    v[a] = static_cast<double>(ldg<real>(s.fld[0][F_VX + a],
-                                         i + (buf ? (std::is_same<P, C32>::value
-                                                         ? s.bstride4 / 4u : s.bstride8 / 8u)
-                                                  : 0u)));
+  if constexpr (std::is_same<P, C32>::value) {
+    const uint32_t o = 4u * (i + (buf ? s.bstride16 / 16u : 0u));
+    for (int a = 0; a < 3; ++a) v[a] = static_cast<double>(ldg<float>(s.fld[0][F_VX], o + a));
+  } else {
+    const uint32_t o = i + (buf ? s.bstride8 / 8u : 0u);
+    for (int a = 0; a < 3; ++a) v[a] = static_cast<double>(ldg<real>(s.fld[0][F_VX + a], o));
+  }
 }
 
 template <class P>
 __device__ __forceinline__ void store_v(const SpeciesDev& s, int buf, uint32_t i, const double v[3]) {
   using real = typename CReal<P>::type;
-  const uint32_t o = i + (buf ? (std::is_same<P, C32>::value ? s.bstride4 / 4u : s.bstride8 / 8u)
-                              : 0u);
-  for (int a = 0; a < 3; ++a) stg<real>(s.fld[0][F_VX + a], o, static_cast<real>(v[a]));
+  if constexpr (std::is_same<P, C32>::value) {
+    const uint32_t o = 4u * (i + (buf ? s.bstride16 / 16u : 0u));
+    for (int a = 0; a < 3; ++a) stg<float>(s.fld[0][F_VX], o + a, static_cast<float>(v[a]));
+  } else {
+    const uint32_t o = i + (buf ? s.bstride8 / 8u : 0u);
+    for (int a = 0; a < 3; ++a) stg<real>(s.fld[0][F_VX + a], o, static_cast<real>(v[a]));
+  }
 }
 
+template <class P>
 __device__ __forceinline__ uint32_t load_id(const SpeciesDev& s, int buf, uint32_t i) {
-  return ldg<uint32_t>(s.fld[0][F_ID], i + (buf ? s.bstride4 / 4u : 0u));
+  if constexpr (std::is_same<P, C32>::value)
+    return ldg<uint32_t>(s.fld[0][F_VX], 4u * (i + (buf ? s.bstride16 / 16u : 0u)) + 3u);
+  else
+    return ldg<uint32_t>(s.fld[0][F_ID], i + (buf ? s.bstride4 / 4u : 0u));
 }
 
 // One pair collision in SI-free form: velocities in cells / step, `coef` carries
@@ -139,14 +150,14 @@ __global__ __launch_bounds__(256) void k_coulomb(const SimDev* __restrict__ simp
     bool touched[2][2] = {{false, false}, {false, false}};
     // like pairs
     if (ee && have[0][1]) {
-      const uint32_t id = load_id(se, q, e0 + k0);
+      const uint32_t id = load_id<P>(se, q, e0 + k0);
       pair_collide(v[0][0], v[0][1], dd.coul_coef[0], static_cast<double>(ne) * dd.coul_dens,
                    dd.vunit, 0.5, 0.5, philox(id, step32, 0u, 2u, se.key0, se.key1),
                    philox(id, step32, 1u, 2u, se.key0, se.key1));
       touched[0][0] = touched[0][1] = true;
     }
     if (ii && have[1][1]) {
-      const uint32_t id = load_id(si, q, i0 + k0);
+      const uint32_t id = load_id<P>(si, q, i0 + k0);
       pair_collide(v[1][0], v[1][1], dd.coul_coef[1], static_cast<double>(ni) * dd.coul_dens,
                    dd.vunit, 0.5, 0.5, philox(id, step32, 0u, 2u, si.key0, si.key1),
                    philox(id, step32, 1u, 2u, si.key0, si.key1));
@@ -156,7 +167,7 @@ __global__ __launch_bounds__(256) void k_coulomb(const SimDev* __restrict__ simp
     if (ei) {
       for (int m = 0; m < 2; ++m) {
         if (k0 + m >= np) break;
-        const uint32_t id = load_id(se, q, e0 + k0 + m);
+        const uint32_t id = load_id<P>(se, q, e0 + k0 + m);
         pair_collide(v[0][m], v[1][m], dd.coul_coef[2], static_cast<double>(np) * dd.coul_dens,
                      dd.vunit, dd.mfrac_e, dd.mfrac_i,
                      philox(id, step32, 2u, 2u, se.key0, se.key1),

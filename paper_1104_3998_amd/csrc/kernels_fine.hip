@@ -65,11 +65,12 @@ __device__ __forceinline__ void fine_copy(const SpeciesDev& s, uint32_t a, uint3
   if constexpr (std::is_same<P, F32>::value) {
     stg<int>(s.fine[F32_CELL], b, ldg<int>(s.fine[F32_CELL], a));
     stg<float>(s.fine[F32_OFF], b, ldg<float>(s.fine[F32_OFF], a));
+    stg<uint4>(s.fine[F_VX], b, ldg<uint4>(s.fine[F_VX], a));  // velocity and id record
   } else {
     stg<double>(s.fine[F64_X], b, ldg<double>(s.fine[F64_X], a));
+    for (int f = F_VX; f <= F_VZ; ++f) stg<real>(s.fine[f], b, ldg<real>(s.fine[f], a));
+    stg<uint32_t>(s.fine[F_ID], b, ldg<uint32_t>(s.fine[F_ID], a));
   }
-  for (int f = F_VX; f <= F_VZ; ++f) stg<real>(s.fine[f], b, ldg<real>(s.fine[f], a));
-  stg<uint32_t>(s.fine[F_ID], b, ldg<uint32_t>(s.fine[F_ID], a));
 }
 
 // sorting cell of a particle in cell c
@@ -299,11 +300,14 @@ __global__ __launch_bounds__(kSolveWG) void k_fine_births(const SimDev* __restri
       if constexpr (std::is_same<P, F32>::value) {
         stg<int>(s.fine[F32_CELL], b, cell);
         stg<float>(s.fine[F32_OFF], b, pos);
+        uint4 v = ldg<uint4>(src[F_VX], si);  // the staged birth's velocity record
+        v.w = nid + rank;
+        stg<uint4>(s.fine[F_VX], b, v);
       } else {
         stg<double>(s.fine[F64_X], b, pos);
+        for (int f = F_VX; f <= F_VZ; ++f) stg<real>(s.fine[f], b, ldg<real>(src[f], si));
+        stg<uint32_t>(s.fine[F_ID], b, nid + rank);
       }
-      for (int f = F_VX; f <= F_VZ; ++f) stg<real>(s.fine[f], b, ldg<real>(src[f], si));
-      stg<uint32_t>(s.fine[F_ID], b, nid + rank);
       // deposit (fixed point, order-free)
       const double fr = std::is_same<P, F32>::value ? static_cast<double>(pos)
                                                      : static_cast<double>(pos) - floor(static_cast<double>(pos));
@@ -343,11 +347,12 @@ __global__ __launch_bounds__(kFineWG) void k_fine_scatter(const SimDev* __restri
     if constexpr (std::is_same<P, F32>::value) {
       stg<int>(s.fine[F32_CELL], o, ldg<int>(f[F32_CELL], i));
       stg<float>(s.fine[F32_OFF], o, ldg<float>(f[F32_OFF], i));
+      stg<uint4>(s.fine[F_VX], o, ldg<uint4>(f[F_VX], i));  // velocity and id record
     } else {
       stg<double>(s.fine[F64_X], o, ldg<double>(f[F64_X], i));
+      for (int q = F_VX; q <= F_VZ; ++q) stg<real>(s.fine[q], o, ldg<real>(f[q], i));
+      stg<uint32_t>(s.fine[F_ID], o, ldg<uint32_t>(f[F_ID], i));
     }
-    for (int q = F_VX; q <= F_VZ; ++q) stg<real>(s.fine[q], o, ldg<real>(f[q], i));
-    stg<uint32_t>(s.fine[F_ID], o, ldg<uint32_t>(f[F_ID], i));
   }
   if (threadIdx.x == 0) s.fcnt[k] = n;
 }

@@ -44,14 +44,14 @@ __device__ __forceinline__ void copy_record(void GM* const* src, uint32_t i, voi
   if constexpr (std::is_same<P, S32>::value) {
     static_cast<int GM*>(dst[F32_CELL])[j] = static_cast<const int GM*>(src[F32_CELL])[i];
     static_cast<float GM*>(dst[F32_OFF])[j] = static_cast<const float GM*>(src[F32_OFF])[i];
-    for (int f = F_VX; f <= F_VZ; ++f)
-      static_cast<float GM*>(dst[f])[j] = static_cast<const float GM*>(src[f])[i];
+    // velocity and id: one 16-byte record
+    static_cast<uint4 GM*>(dst[F_VX])[j] = static_cast<const uint4 GM*>(src[F_VX])[i];
   } else {
     static_cast<double GM*>(dst[F64_X])[j] = static_cast<const double GM*>(src[F64_X])[i];
     for (int f = F_VX; f <= F_VZ; ++f)
       static_cast<double GM*>(dst[f])[j] = static_cast<const double GM*>(src[f])[i];
+    static_cast<uint32_t GM*>(dst[F_ID])[j] = static_cast<const uint32_t GM*>(src[F_ID])[i];
   }
-  static_cast<uint32_t GM*>(dst[F_ID])[j] = static_cast<const uint32_t GM*>(src[F_ID])[i];
 }
 
 // ------------------------------------------------------------------------------------
@@ -93,12 +93,14 @@ __global__ __launch_bounds__(256) void k_load(const SimDev* __restrict__ simp, i
     const double c = floor(x);
     static_cast<int GM*>(f[F32_CELL])[i] = static_cast<int>(c);
     static_cast<float GM*>(f[F32_OFF])[i] = __double2float_rz(x - c);
-    for (int a = 0; a < 3; ++a) static_cast<float GM*>(f[F_VX + a])[i] = static_cast<float>(v[a]);
+    static_cast<uint4 GM*>(f[F_VX])[i] =
+        make_uint4(__float_as_uint(static_cast<float>(v[0])), __float_as_uint(static_cast<float>(v[1])),
+                   __float_as_uint(static_cast<float>(v[2])), i);
   } else {
     static_cast<double GM*>(f[F64_X])[i] = x;
     for (int a = 0; a < 3; ++a) static_cast<double GM*>(f[F_VX + a])[i] = v[a];
+    static_cast<uint32_t GM*>(f[F_ID])[i] = i;
   }
-  static_cast<uint32_t GM*>(f[F_ID])[i] = i;
 }
 
 // ------------------------------------------------------------------------------------
@@ -326,8 +328,8 @@ __global__ __launch_bounds__(256) void k_halfstep(const SimDev* __restrict__ sim
     const float ep = a + b;
     const float hk = 0.5f * s.kappa_f;
     const float dv = hk * ep;
-    float* vx = static_cast<float GM*>(f[F_VX]);
-    vx[i] = vx[i] - dv;
+    float* vx = static_cast<float GM*>(f[F_VX]);  // velocity records: 4 floats each
+    vx[4 * static_cast<size_t>(i)] = vx[4 * static_cast<size_t>(i)] - dv;
   } else {
     const double x = static_cast<const double GM*>(f[F64_X])[i];
     if (!(x >= 0.0 && x < static_cast<double>(N))) return;

@@ -32,10 +32,11 @@ struct P64 {};
 // One particle array (or staging set) as the kernels address it: the field pointers of
 // buffer 0 (in scalar registers for the whole particle loop) and the byte distance to the
 // array wanted, so that the two buffers of a field share one base pointer and differ only
-// in a 32-bit offset (boff4 for 4-byte fields, boff8 for 8-byte ones).
+// in a 32-bit offset (boff4 for 4-byte fields, boff8 for 8-byte ones, boff16 for the
+// FP32 velocity records).
 struct RecPtr {
   void GM* f[6];
-  uint32_t boff4, boff8;
+  uint32_t boff4, boff8, boff16;
 };
 
 // buffer b of the species' particle arrays (a fine-sorted species has one set of arrays,
@@ -45,13 +46,14 @@ __device__ __forceinline__ RecPtr rec_buf(const SpeciesDev CM* s, int b) {
   if (s->mode == kModeFine) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) r.f[k] = s->fine[k];
-    r.boff4 = r.boff8 = 0u;
+    r.boff4 = r.boff8 = r.boff16 = 0u;
     return r;
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) r.f[k] = s->fld[0][k];
   r.boff4 = b ? s->bstride4 : 0u;
   r.boff8 = b ? s->bstride8 : 0u;
+  r.boff16 = b ? s->bstride16 : 0u;
   return r;
 }
 
@@ -60,7 +62,7 @@ __device__ __forceinline__ RecPtr rec_stage(const SpeciesDev CM* s, int k6) {
   RecPtr r;
 #pragma unroll
   for (int k = 0; k < 6; ++k) r.f[k] = s->stage[k6][k];
-  r.boff4 = r.boff8 = 0u;
+  r.boff4 = r.boff8 = r.boff16 = 0u;
   return r;
 }
 
@@ -75,6 +77,16 @@ __device__ __forceinline__ void sto(void GM* base, uint32_t off, T v) {
   *reinterpret_cast<T GM*>(reinterpret_cast<char GM*>(base) + off) = v;
 }
 
+// byte offset of FP32 velocity record i (vx, vy, vz, id; from the vx field's pointer)
+__device__ __forceinline__ uint32_t vel_off(const RecPtr& f, uint32_t i) {
+  return f.boff16 + i * 16u;
+}
+
+// an FP32 velocity written with one 12-byte store
+struct alignas(4) Vel3 {
+  float x, y, z;
+};
+
 template <class P>
 struct Part0;
 template <>
@@ -86,16 +98,43 @@ struct Part0<P64> {
   using real = double;
 };
 
-// byte offset of element i of a real-valued field of the layout P
+// Velocity of record i (the MCC pass's update of a collided particle): FP32 one 12-byte
+// store into the record's line, FP64 one store per field array.
 template <class P>
-__device__ __forceinline__ uint32_t real_off(const RecPtr& f, uint32_t i);
-template <>
-__device__ __forceinline__ uint32_t real_off<P32>(const RecPtr& f, uint32_t i) {
-  return f.boff4 + i * 4u;
+__device__ __forceinline__ void store_velocity(const RecPtr& f, uint32_t i,
+                                               const typename Part0<P>::real v[3]) {
+  if constexpr (std::is_same<P, P32>::value) {
+    sto<Vel3>(f.f[F_VX], vel_off(f, i), Vel3{v[0], v[1], v[2]});
+  } else {
+    const uint32_t o8 = f.boff8 + i * 8u;
+    sto<double>(f.f[F_VX], o8, v[0]);
+    sto<double>(f.f[F_VY], o8, v[1]);
+    sto<double>(f.f[F_VZ], o8, v[2]);
+  }
 }
-template <>
-__device__ __forceinline__ uint32_t real_off<P64>(const RecPtr& f, uint32_t i) {
-  return f.boff8 + i * 8u;
+
+// Velocity of record i of a staging set (births, emitted electrons).
+template <class P>
+__device__ __forceinline__ void load_velocity(const RecPtr& f, uint32_t i,
+                                              typename Part0<P>::real v[3]) {
+  if constexpr (std::is_same<P, P32>::value) {
+    const Vel3 q = ldo<Vel3>(f.f[F_VX], vel_off(f, i));
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+  } else {
+    const uint32_t o8 = f.boff8 + i * 8u;
+    v[0] = ldo<double>(f.f[F_VX], o8);
+    v[1] = ldo<double>(f.f[F_VY], o8);
+    v[2] = ldo<double>(f.f[F_VZ], o8);
+  }
+}
+
+// byte offset of record i's id (from the id field's pointer)
+template <class P>
+__device__ __forceinline__ uint32_t id_off(const RecPtr& f, uint32_t i) {
+  if constexpr (std::is_same<P, P32>::value) return vel_off(f, i);
+  else return f.boff4 + i * 4u;
 }
 
 // One MCC candidate record: output slot, id, post-push cell, position word and velocity.
@@ -158,10 +197,11 @@ struct Part<P32> {
     const uint32_t o = f.boff4 + i * 4u;
     cell = ldo<int>(f.f[F32_CELL], o);
     off = ldo<float>(f.f[F32_OFF], o);
-    vx = ldo<float>(f.f[F_VX], o);
-    vy = ldo<float>(f.f[F_VY], o);
-    vz = ldo<float>(f.f[F_VZ], o);
-    id = ldo<uint32_t>(f.f[F_ID], o);
+    const uint4 v = ldo<uint4>(f.f[F_VX], vel_off(f, i));
+    vx = __uint_as_float(v.x);
+    vy = __uint_as_float(v.y);
+    vz = __uint_as_float(v.z);
+    id = v.w;
   }
 };
 
@@ -182,7 +222,8 @@ struct Part<P64> {
 
 // Stores one record: cell d and offset (FP32) or absolute x (FP64), velocity, and the id
 // unless kWithId is false (birth staging keeps no id: k_finalize numbers the births when it
-// appends them, and the staging arrays have no id field).
+// appends them; the FP64 staging arrays have no id field, the FP32 ones get 0 in the
+// record's id word).
 template <class P, bool kWithId = true>
 __device__ __forceinline__ void store_record(const RecPtr& f, uint32_t i, int d,
                                              typename Part<P>::real pos,
@@ -193,17 +234,17 @@ __device__ __forceinline__ void store_record(const RecPtr& f, uint32_t i, int d,
   if constexpr (std::is_same<P, P32>::value) {
     sto<int>(f.f[F32_CELL], o4, d);
     sto<float>(f.f[F32_OFF], o4, pos);
-    sto<float>(f.f[F_VX], o4, vx);
-    sto<float>(f.f[F_VY], o4, vy);
-    sto<float>(f.f[F_VZ], o4, vz);
+    sto<uint4>(f.f[F_VX], vel_off(f, i),
+               make_uint4(__float_as_uint(vx), __float_as_uint(vy), __float_as_uint(vz),
+                          kWithId ? id : 0u));
   } else {
     const uint32_t o8 = f.boff8 + i * 8u;
     sto<double>(f.f[F64_X], o8, pos);
     sto<double>(f.f[F_VX], o8, vx);
     sto<double>(f.f[F_VY], o8, vy);
     sto<double>(f.f[F_VZ], o8, vz);
+    if constexpr (kWithId) sto<uint32_t>(f.f[F_ID], o4, id);
   }
-  if constexpr (kWithId) sto<uint32_t>(f.f[F_ID], o4, id);
 }
 
 // In-place update of a fine-sorted particle's position and v_x (the other fields do not
@@ -217,7 +258,7 @@ __device__ __forceinline__ void store_in_place(const RecPtr& f, uint32_t i, bool
   if constexpr (std::is_same<P, P32>::value) {
     sto<int>(f.f[F32_CELL], o4, alive ? d : -1);
     sto<float>(f.f[F32_OFF], o4, pos);
-    sto<float>(f.f[F_VX], o4, vx);
+    sto<float>(f.f[F_VX], vel_off(f, i), vx);
   } else {
     const uint32_t o8 = f.boff8 + i * 8u;
     sto<double>(f.f[F64_X], o8, alive ? pos : -1.0);
@@ -379,7 +420,7 @@ struct PushIn<P32> {
     const uint32_t o = f.boff4 + i * 4u;
     cell = ldo<int>(f.f[F32_CELL], o);
     off = ldo<float>(f.f[F32_OFF], o);
-    vx = ldo<float>(f.f[F_VX], o);
+    vx = ldo<float>(f.f[F_VX], vel_off(f, i));
   }
 };
 
@@ -955,7 +996,7 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
           real pos, vxn;
           if (valid) st = push_particle<P, false>(s, dd, Elds, r, q, d, pos, vxn);
           if (s.t_refl && (st == 1 || st == 2))
-            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], in.boff4 + i * 4u), step32, st,
+            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], id_off<P>(in, i)), step32, st,
                                     d, pos, vxn);
           const int k = st == 0 ? window_slot(s, tt.y, d) : -1;
           const bool near = k >= 0;
@@ -989,7 +1030,7 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
           real pos, vxn;
           if (valid) st = push_particle<P, true>(s, dd, Elds, r, q, d, pos, vxn);
           if (s.t_refl && (st == 1 || st == 2))
-            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], in.boff4 + i * 4u), step32, st,
+            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], id_off<P>(in, i)), step32, st,
                                     d, pos, vxn);
           cnt += static_cast<uint32_t>(__popcll(__ballot(st == 0)));
         });
@@ -1003,7 +1044,7 @@ __global__ __launch_bounds__(kWG) void k_hist(const SimDev* __restrict__ simp) {
           real pos, vxn;
           if (valid) st = push_particle<P, true>(s, dd, Elds, r, q, d, pos, vxn);
           if (s.t_refl && (st == 1 || st == 2))
-            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], in.boff4 + i * 4u), step32, st,
+            st = reflect_at_wall<P>(s, ldo<uint32_t>(in.f[F_ID], id_off<P>(in, i)), step32, st,
                                     d, pos, vxn);
           if (st == 0) atomicAdd(&row[d], 1u);
         });
@@ -1957,10 +1998,7 @@ __global__ __launch_bounds__(kT) void k_collide(const SimDev* __restrict__ simp)
         const int ch = collide<P>(s, c.y, step32, b0.y, b0.z, v, vs, vi);
         if (ch > 0) {
           atomicAdd(&coll[ch - 1], 1u);
-          const uint32_t o = real_off<P>(out, dst);
-          sto<real>(out.f[F_VX], o, v[0]);
-          sto<real>(out.f[F_VY], o, v[1]);
-          sto<real>(out.f[F_VZ], o, v[2]);
+          store_velocity<P>(out, dst, v);
           born = s.sp == 0 && ch == 3;
           parent = c.y;
         }
@@ -2018,7 +2056,7 @@ __global__ __launch_bounds__(kWG) void k_emit(const SimDev* __restrict__ simp) {
   RecPtr out;
 #pragma unroll
   for (int k = 0; k < 6; ++k) out.f[k] = s.em_stage[k];
-  out.boff4 = out.boff8 = 0u;
+  out.boff4 = out.boff8 = out.boff16 = 0u;
   uint32_t n_wall[2] = {0u, 0u};
   for (int w = 0; w < kWaves; ++w) {
     const int unit = tt.y * kWaves + w;
@@ -2369,8 +2407,9 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
           } else {
             pos = ldg<double>(src.f[F64_X], si);
           }
-          store_record<P>(dst, n_surv + b, cell, pos, ldg<real>(src.f[F_VX], si),
-                          ldg<real>(src.f[F_VY], si), ldg<real>(src.f[F_VZ], si), nid + b);
+          real v[3];
+          load_velocity<P>(src, si, v);
+          store_record<P>(dst, n_surv + b, cell, pos, v[0], v[1], v[2], nid + b);
           if constexpr (std::is_same<P, P64>::value) cell = static_cast<int>(floor(pos));
           if (cell >= 0 && cell < s.n_cells) far_deposit<P>(s, cell, pos);
         }
@@ -2385,7 +2424,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
       RecPtr src;
 #pragma unroll
       for (int k = 0; k < 6; ++k) src.f[k] = se.em_stage[k];
-      src.boff4 = src.boff8 = 0u;
+      src.boff4 = src.boff8 = src.boff16 = 0u;
       const RecPtr dst = rec_buf(&sim.sp[tt.x - 1], q);
       for (int w = 0; w < kWaves; ++w) {
         const int unit = u * kWaves + w;
@@ -2403,8 +2442,9 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
             pos = ldg<double>(src.f[F64_X], si);
             cell = static_cast<int>(floor(pos));
           }
-          store_record<P>(dst, n_surv + b, cell, pos, ldg<real>(src.f[F_VX], si),
-                          ldg<real>(src.f[F_VY], si), ldg<real>(src.f[F_VZ], si), nid + b);
+          real v[3];
+          load_velocity<P>(src, si, v);
+          store_record<P>(dst, n_surv + b, cell, pos, v[0], v[1], v[2], nid + b);
           if (cell >= 0 && cell < el.n_cells) far_deposit<P>(el, cell, pos);
         }
       }
