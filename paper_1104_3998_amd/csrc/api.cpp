@@ -93,7 +93,6 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
     choose_tiles(cfgs[d], pl->der[d], &pl->tiles[2 * d]);
   }
   const bool fp32 = cfgs[0].precision == PIC_FP32_OFFSET;
-  const size_t rs = fp32 ? 4 : 8;  // bytes of a real
   pl->li.lag = cfgs[0].sort_mode == PIC_SORT_LAG;
   Carver cv{ws};
   pl->sp.assign(2 * n, SpeciesDev{});
@@ -175,32 +174,36 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       const size_t cap1 = static_cast<size_t>(cap) + 1;
       // the two buffers of a field are one allocation, buffer 1 a fixed distance above
       // buffer 0, so the kernels reach both from one base pointer
+      // velocity records: FP32 16 bytes (vx, vy, vz, id), FP64 24 bytes (vx, vy, vz);
+      // the buffer distance a multiple of 256 and of the record size
+      const size_t rv = fp32 ? 16 : 24;
       const size_t st4 = align_up(4 * cap1, 256), st8 = align_up(8 * cap1, 256);
-      const size_t st16 = align_up(16 * cap1, 256);
+      const size_t stv = align_up(rv * cap1, fp32 ? 256 : 768);
       S.bstride4 = static_cast<uint32_t>(st4);
       S.bstride8 = static_cast<uint32_t>(st8);
-      S.bstride16 = static_cast<uint32_t>(st16);
+      S.bstridev = static_cast<uint32_t>(stv);
+      const int last_rec = fp32 ? F_ID : F_VZ;  // the last field in the velocity record
       for (int f = 0; f < 6; ++f) {
         if (!fp32 && f == 1) {
           S.fld[0][f] = S.fld[1][f] = nullptr;
           continue;
         }
-        if (fp32 && f >= F_VX) continue;  // the velocity records, below
+        if (f >= F_VX && f <= last_rec) continue;  // the velocity records, below
         const size_t st = (fp32 || f == F_ID) ? st4 : st8;
         char* pair = cv.take<char>(2 * st);
         S.fld[0][f] = pair;
         S.fld[1][f] = pair ? pair + st : nullptr;
       }
-      if (fp32) {
-        char* pair = cv.take<char>(2 * st16);
+      {
+        char* pair = cv.take<char>(2 * stv);
         for (int b = 0; b < 2; ++b)
-          for (int f = F_VX; f <= F_ID; ++f)
-            S.fld[b][f] = pair ? pair + b * st16 + 4 * (f - F_VX) : nullptr;
+          for (int f = F_VX; f <= last_rec; ++f)
+            S.fld[b][f] = pair ? pair + b * stv + (rv / 4) * (f - F_VX) : nullptr;
       }
-      // FP32 velocity records of n elements: vx, vy, vz (and id) pointers into one array
+      // velocity records of n elements: the vx, vy, vz (FP32 also id) pointers into one array
       auto vel_records = [&](void** fl, size_t n) {
-        char* v = cv.take<char>(16 * n);
-        for (int f = F_VX; f <= F_ID; ++f) fl[f] = v ? v + 4 * (f - F_VX) : nullptr;
+        char* v = cv.take<char>(rv * n);
+        for (int f = F_VX; f <= last_rec; ++f) fl[f] = v ? v + (rv / 4) * (f - F_VX) : nullptr;
       };
       if (s == 0) {
         for (int b = 0; b < 2; ++b) {
@@ -211,7 +214,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
           } else {
             S.stage[b][F64_X] = cv.take<double>(cap);
             S.stage[b][1] = nullptr;
-            for (int f = F_VX; f <= F_VZ; ++f) S.stage[b][f] = cv.take<char>(rs * cap);
+            vel_records(S.stage[b], cap);
           }
           S.stage[b][F_ID] = nullptr;
         }
@@ -222,10 +225,10 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
       if (c.sort_mode == PIC_SORT_FINE) {
         for (int f = 0; f < 6; ++f) {
           if (!fp32 && f == 1) continue;
-          if (fp32 && f >= F_VX) continue;
+          if (f >= F_VX && f <= last_rec) continue;
           S.fine[f] = cv.take<char>(((fp32 || f == F_ID) ? 4 : 8) * cap1);
         }
-        if (fp32) vel_records(S.fine, cap1);
+        vel_records(S.fine, cap1);
         S.fcnt = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles));
         S.flv = cv.take<uint32_t>(static_cast<size_t>(tc.n_tiles));
         if (s == 0) {
@@ -289,7 +292,7 @@ int build_plan(const pic_config* cfgs, int n, char* ws, Plan* pl, std::string* w
           S.em_stage[F_ID] = nullptr;
         } else {
           S.em_stage[F64_X] = cv.take<double>(cap);
-          for (int f = F_VX; f <= F_VZ; ++f) S.em_stage[f] = cv.take<char>(rs * cap);
+          vel_records(S.em_stage, cap);
         }
         S.ab_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
         S.em_cnt = cv.take<uint32_t>(static_cast<size_t>(ntt) * kWaves);
@@ -741,6 +744,18 @@ static void split_vel(const VelRec& r, size_t o, float* vx, float* vy, float* vz
   if (id) id[o] = r.id;
 }
 
+// FP64 velocity records (vx, vy, vz)
+struct VelRec64 {
+  double vx, vy, vz;
+};
+static_assert(sizeof(VelRec64) == 24, "24-byte velocity records");
+
+static void split_vel64(const VelRec64& r, size_t o, double* vx, double* vy, double* vz) {
+  if (vx) vx[o] = r.vx;
+  if (vy) vy[o] = r.vy;
+  if (vz) vz[o] = r.vz;
+}
+
 static uint64_t device_step(pic_sim* sim, int* rc) {
   unsigned long long st = 0;
   *rc = d2h(sim, &st, sim->pl.sim.step, 1);
@@ -944,9 +959,9 @@ static int fine_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, pic_
     return PIC_OK;
   } else {
     if ((rc = fine_gather(sim, S, f[F64_X], st->x[s], cnt))) return rc;
-    if ((rc = fine_gather(sim, S, f[F_VX], st->vx[s], cnt))) return rc;
-    if ((rc = fine_gather(sim, S, f[F_VY], st->vy[s], cnt))) return rc;
-    if ((rc = fine_gather(sim, S, f[F_VZ], st->vz[s], cnt))) return rc;
+    std::vector<VelRec64> rec(static_cast<size_t>(n));
+    if ((rc = fine_gather(sim, S, f[F_VX], rec.data(), cnt))) return rc;
+    for (size_t i = 0; i < rec.size(); ++i) split_vel64(rec[i], i, st->vx[s], st->vy[s], st->vz[s]);
   }
   return fine_gather(sim, S, f[F_ID], st->id[s], cnt);
 }
@@ -988,9 +1003,11 @@ static int lag_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, int p
     if ((rc = d2h(sim, x.data(), static_cast<const double*>(f[F64_X]), nt))) return rc;
     for (uint32_t i = 0; i < nt; ++i) live[i] = x[i] >= 0.0;
     if ((rc = lag_gather(sim, f[F64_X], st->x[s], live))) return rc;
-    if ((rc = lag_gather(sim, f[F_VX], st->vx[s], live))) return rc;
-    if ((rc = lag_gather(sim, f[F_VY], st->vy[s], live))) return rc;
-    if ((rc = lag_gather(sim, f[F_VZ], st->vz[s], live))) return rc;
+    size_t n_live = 0;
+    for (char l : live) n_live += l ? 1 : 0;
+    std::vector<VelRec64> rec(n_live);
+    if ((rc = lag_gather(sim, f[F_VX], rec.data(), live))) return rc;
+    for (size_t i = 0; i < rec.size(); ++i) split_vel64(rec[i], i, st->vx[s], st->vy[s], st->vz[s]);
   }
   return lag_gather(sim, f[F_ID], st->id[s], live);
 }
@@ -1049,9 +1066,11 @@ extern "C" int pic_get_state(pic_sim* sim, int d, pic_state* st) {
       }
     } else {
       if (st->x[s] && (rc = d2h(sim, st->x[s], static_cast<const double*>(f[F64_X]), nt))) return rc;
-      if (st->vx[s] && (rc = d2h(sim, st->vx[s], static_cast<const double*>(f[F_VX]), nt))) return rc;
-      if (st->vy[s] && (rc = d2h(sim, st->vy[s], static_cast<const double*>(f[F_VY]), nt))) return rc;
-      if (st->vz[s] && (rc = d2h(sim, st->vz[s], static_cast<const double*>(f[F_VZ]), nt))) return rc;
+      if (st->vx[s] || st->vy[s] || st->vz[s]) {
+        std::vector<VelRec64> rec(nt);
+        if ((rc = d2h(sim, rec.data(), static_cast<const VelRec64*>(f[F_VX]), nt))) return rc;
+        for (uint32_t i = 0; i < nt; ++i) split_vel64(rec[i], i, st->vx[s], st->vy[s], st->vz[s]);
+      }
       if (st->id[s] && (rc = d2h(sim, st->id[s], static_cast<const uint32_t*>(f[F_ID]), nt))) return rc;
     }
     if (st->w[s] && (rc = d2h(sim, st->w[s], D.w[s], D.n_nodes))) return rc;
@@ -1137,9 +1156,9 @@ extern "C" int pic_set_state(pic_sim* sim, int d, const pic_state* st) {
       if ((rc = h2d(sim, static_cast<VelRec*>(f[F_VX]), rec.data(), n))) return rc;
     } else {
       if ((rc = h2d(sim, static_cast<double*>(f[F64_X]), st->x[s], n))) return rc;
-      if ((rc = h2d(sim, static_cast<double*>(f[F_VX]), st->vx[s], n))) return rc;
-      if ((rc = h2d(sim, static_cast<double*>(f[F_VY]), st->vy[s], n))) return rc;
-      if ((rc = h2d(sim, static_cast<double*>(f[F_VZ]), st->vz[s], n))) return rc;
+      std::vector<VelRec64> rec(n);
+      for (uint32_t i = 0; i < n; ++i) rec[i] = VelRec64{st->vx[s][i], st->vy[s][i], st->vz[s][i]};
+      if ((rc = h2d(sim, static_cast<VelRec64*>(f[F_VX]), rec.data(), n))) return rc;
       if ((rc = h2d(sim, static_cast<uint32_t*>(f[F_ID]), st->id[s], n))) return rc;
     }
     const uint32_t cnt[2] = {n, ns};

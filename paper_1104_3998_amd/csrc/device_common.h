@@ -370,6 +370,15 @@ __device__ __forceinline__ void stg(void GM* base, uint32_t i, T v) {
   *reinterpret_cast<T GM*>(reinterpret_cast<char GM*>(base) + i * static_cast<uint32_t>(sizeof(T))) = v;
 }
 
+// A velocity written or copied as one record (FP32: the first 12 bytes of the 16-byte
+// record; FP64: the whole 24-byte record).
+struct alignas(4) Vel3 {
+  float x, y, z;
+};
+struct alignas(8) Vel3d {
+  double x, y, z;
+};
+
 // Index of this thread's wave in the workgroup, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);

@@ -44,35 +44,34 @@ struct CReal<C64> {
   using type = double;
 };
 
-// FP32: vx, vy, vz are words 0-2 of the particle's 16-byte velocity record, the id word 3
+// FP32: vx, vy, vz are words 0-2 of the particle's 16-byte velocity record, the id word 3;
+// FP64: the three doubles of its 24-byte record
 template <class P>
 __device__ __forceinline__ void load_v(const SpeciesDev& s, int buf, uint32_t i, double v[3]) {
-  using real = typename CReal<P>::type;
   if constexpr (std::is_same<P, C32>::value) {
-    const uint32_t o = 4u * (i + (buf ? s.bstride16 / 16u : 0u));
+    const uint32_t o = 4u * (i + (buf ? s.bstridev / 16u : 0u));
     for (int a = 0; a < 3; ++a) v[a] = static_cast<double>(ldg<float>(s.fld[0][F_VX], o + a));
   } else {
-    const uint32_t o = i + (buf ? s.bstride8 / 8u : 0u);
-    for (int a = 0; a < 3; ++a) v[a] = static_cast<double>(ldg<real>(s.fld[0][F_VX + a], o));
+    const uint32_t o = 3u * (i + (buf ? s.bstridev / 24u : 0u));
+    for (int a = 0; a < 3; ++a) v[a] = ldg<double>(s.fld[0][F_VX], o + a);
   }
 }
 
 template <class P>
 __device__ __forceinline__ void store_v(const SpeciesDev& s, int buf, uint32_t i, const double v[3]) {
-  using real = typename CReal<P>::type;
   if constexpr (std::is_same<P, C32>::value) {
-    const uint32_t o = 4u * (i + (buf ? s.bstride16 / 16u : 0u));
+    const uint32_t o = 4u * (i + (buf ? s.bstridev / 16u : 0u));
     for (int a = 0; a < 3; ++a) stg<float>(s.fld[0][F_VX], o + a, static_cast<float>(v[a]));
   } else {
-    const uint32_t o = i + (buf ? s.bstride8 / 8u : 0u);
-    for (int a = 0; a < 3; ++a) stg<real>(s.fld[0][F_VX + a], o, static_cast<real>(v[a]));
+    const uint32_t o = 3u * (i + (buf ? s.bstridev / 24u : 0u));
+    for (int a = 0; a < 3; ++a) stg<double>(s.fld[0][F_VX], o + a, v[a]);
   }
 }
 
 template <class P>
 __device__ __forceinline__ uint32_t load_id(const SpeciesDev& s, int buf, uint32_t i) {
   if constexpr (std::is_same<P, C32>::value)
-    return ldg<uint32_t>(s.fld[0][F_VX], 4u * (i + (buf ? s.bstride16 / 16u : 0u)) + 3u);
+    return ldg<uint32_t>(s.fld[0][F_VX], 4u * (i + (buf ? s.bstridev / 16u : 0u)) + 3u);
   else
     return ldg<uint32_t>(s.fld[0][F_ID], i + (buf ? s.bstride4 / 4u : 0u));
 }

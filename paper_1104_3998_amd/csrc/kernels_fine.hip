@@ -68,7 +68,7 @@ __device__ __forceinline__ void fine_copy(const SpeciesDev& s, uint32_t a, uint3
     stg<uint4>(s.fine[F_VX], b, ldg<uint4>(s.fine[F_VX], a));  // velocity and id record
   } else {
     stg<double>(s.fine[F64_X], b, ldg<double>(s.fine[F64_X], a));
-    for (int f = F_VX; f <= F_VZ; ++f) stg<real>(s.fine[f], b, ldg<real>(s.fine[f], a));
+    stg<Vel3d>(s.fine[F_VX], b, ldg<Vel3d>(s.fine[F_VX], a));
     stg<uint32_t>(s.fine[F_ID], b, ldg<uint32_t>(s.fine[F_ID], a));
   }
 }
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kSolveWG) void k_fine_births(const SimDev* __restri
         stg<uint4>(s.fine[F_VX], b, v);
       } else {
         stg<double>(s.fine[F64_X], b, pos);
-        for (int f = F_VX; f <= F_VZ; ++f) stg<real>(s.fine[f], b, ldg<real>(src[f], si));
+        stg<Vel3d>(s.fine[F_VX], b, ldg<Vel3d>(src[F_VX], si));
         stg<uint32_t>(s.fine[F_ID], b, nid + rank);
       }
       // deposit (fixed point, order-free)
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kFineWG) void k_fine_scatter(const SimDev* __restri
       stg<uint4>(s.fine[F_VX], o, ldg<uint4>(f[F_VX], i));  // velocity and id record
     } else {
       stg<double>(s.fine[F64_X], o, ldg<double>(f[F64_X], i));
-      for (int q = F_VX; q <= F_VZ; ++q) stg<real>(s.fine[q], o, ldg<real>(f[q], i));
+      stg<Vel3d>(s.fine[F_VX], o, ldg<Vel3d>(f[F_VX], i));
       stg<uint32_t>(s.fine[F_ID], o, ldg<uint32_t>(f[F_ID], i));
     }
   }

@@ -48,8 +48,7 @@ __device__ __forceinline__ void copy_record(void GM* const* src, uint32_t i, voi
     static_cast<uint4 GM*>(dst[F_VX])[j] = static_cast<const uint4 GM*>(src[F_VX])[i];
   } else {
     static_cast<double GM*>(dst[F64_X])[j] = static_cast<const double GM*>(src[F64_X])[i];
-    for (int f = F_VX; f <= F_VZ; ++f)
-      static_cast<double GM*>(dst[f])[j] = static_cast<const double GM*>(src[f])[i];
+    static_cast<Vel3d GM*>(dst[F_VX])[j] = static_cast<const Vel3d GM*>(src[F_VX])[i];
     static_cast<uint32_t GM*>(dst[F_ID])[j] = static_cast<const uint32_t GM*>(src[F_ID])[i];
   }
 }
@@ -98,7 +97,7 @@ __global__ __launch_bounds__(256) void k_load(const SimDev* __restrict__ simp, i
                    __float_as_uint(static_cast<float>(v[2])), i);
   } else {
     static_cast<double GM*>(f[F64_X])[i] = x;
-    for (int a = 0; a < 3; ++a) static_cast<double GM*>(f[F_VX + a])[i] = v[a];
+    static_cast<Vel3d GM*>(f[F_VX])[i] = Vel3d{v[0], v[1], v[2]};
     static_cast<uint32_t GM*>(f[F_ID])[i] = i;
   }
 }
@@ -338,8 +337,8 @@ __global__ __launch_bounds__(256) void k_halfstep(const SimDev* __restrict__ sim
     const int cn = (s.periodic && c + 1 == N) ? 0 : c + 1;
     const double fr = x - cc;
     const double ep = (1.0 - fr) * dd.E64[c] + fr * dd.E64[cn];
-    double* vx = static_cast<double GM*>(f[F_VX]);
-    vx[i] = vx[i] - 0.5 * s.kappa * ep;
+    double* vx = static_cast<double GM*>(f[F_VX]);  // velocity records: 3 doubles each
+    vx[3 * static_cast<size_t>(i)] = vx[3 * static_cast<size_t>(i)] - 0.5 * s.kappa * ep;
   }
 }
 

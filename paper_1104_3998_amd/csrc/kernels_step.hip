@@ -32,11 +32,11 @@ struct P64 {};
 // One particle array (or staging set) as the kernels address it: the field pointers of
 // buffer 0 (in scalar registers for the whole particle loop) and the byte distance to the
 // array wanted, so that the two buffers of a field share one base pointer and differ only
-// in a 32-bit offset (boff4 for 4-byte fields, boff8 for 8-byte ones, boff16 for the
+// in a 32-bit offset (boff4 for 4-byte fields, boff8 for 8-byte ones, boffv for the
 // FP32 velocity records).
 struct RecPtr {
   void GM* f[6];
-  uint32_t boff4, boff8, boff16;
+  uint32_t boff4, boff8, boffv;
 };
 
 // buffer b of the species' particle arrays (a fine-sorted species has one set of arrays,
@@ -46,14 +46,14 @@ __device__ __forceinline__ RecPtr rec_buf(const SpeciesDev CM* s, int b) {
   if (s->mode == kModeFine) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) r.f[k] = s->fine[k];
-    r.boff4 = r.boff8 = r.boff16 = 0u;
+    r.boff4 = r.boff8 = r.boffv = 0u;
     return r;
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) r.f[k] = s->fld[0][k];
   r.boff4 = b ? s->bstride4 : 0u;
   r.boff8 = b ? s->bstride8 : 0u;
-  r.boff16 = b ? s->bstride16 : 0u;
+  r.boffv = b ? s->bstridev : 0u;
   return r;
 }
 
@@ -62,7 +62,7 @@ __device__ __forceinline__ RecPtr rec_stage(const SpeciesDev CM* s, int k6) {
   RecPtr r;
 #pragma unroll
   for (int k = 0; k < 6; ++k) r.f[k] = s->stage[k6][k];
-  r.boff4 = r.boff8 = r.boff16 = 0u;
+  r.boff4 = r.boff8 = r.boffv = 0u;
   return r;
 }
 
@@ -77,15 +77,10 @@ __device__ __forceinline__ void sto(void GM* base, uint32_t off, T v) {
   *reinterpret_cast<T GM*>(reinterpret_cast<char GM*>(base) + off) = v;
 }
 
-// byte offset of FP32 velocity record i (vx, vy, vz, id; from the vx field's pointer)
-__device__ __forceinline__ uint32_t vel_off(const RecPtr& f, uint32_t i) {
-  return f.boff16 + i * 16u;
-}
-
-// an FP32 velocity written with one 12-byte store
-struct alignas(4) Vel3 {
-  float x, y, z;
-};
+// byte offset of velocity record i (from the vx field's pointer): FP32 16-byte records
+// (vx, vy, vz, id), FP64 24-byte records (vx, vy, vz)
+template <class P>
+__device__ __forceinline__ uint32_t vel_off(const RecPtr& f, uint32_t i);
 
 template <class P>
 struct Part0;
@@ -98,18 +93,24 @@ struct Part0<P64> {
   using real = double;
 };
 
-// Velocity of record i (the MCC pass's update of a collided particle): FP32 one 12-byte
-// store into the record's line, FP64 one store per field array.
+template <>
+__device__ __forceinline__ uint32_t vel_off<P32>(const RecPtr& f, uint32_t i) {
+  return f.boffv + i * 16u;
+}
+template <>
+__device__ __forceinline__ uint32_t vel_off<P64>(const RecPtr& f, uint32_t i) {
+  return f.boffv + i * 24u;
+}
+
+// Velocity of record i (the MCC pass's update of a collided particle): one 12- or 24-byte
+// store into the record.
 template <class P>
 __device__ __forceinline__ void store_velocity(const RecPtr& f, uint32_t i,
                                                const typename Part0<P>::real v[3]) {
   if constexpr (std::is_same<P, P32>::value) {
-    sto<Vel3>(f.f[F_VX], vel_off(f, i), Vel3{v[0], v[1], v[2]});
+    sto<Vel3>(f.f[F_VX], vel_off<P>(f, i), Vel3{v[0], v[1], v[2]});
   } else {
-    const uint32_t o8 = f.boff8 + i * 8u;
-    sto<double>(f.f[F_VX], o8, v[0]);
-    sto<double>(f.f[F_VY], o8, v[1]);
-    sto<double>(f.f[F_VZ], o8, v[2]);
+    sto<Vel3d>(f.f[F_VX], vel_off<P>(f, i), Vel3d{v[0], v[1], v[2]});
   }
 }
 
@@ -118,22 +119,22 @@ template <class P>
 __device__ __forceinline__ void load_velocity(const RecPtr& f, uint32_t i,
                                               typename Part0<P>::real v[3]) {
   if constexpr (std::is_same<P, P32>::value) {
-    const Vel3 q = ldo<Vel3>(f.f[F_VX], vel_off(f, i));
+    const Vel3 q = ldo<Vel3>(f.f[F_VX], vel_off<P>(f, i));
     v[0] = q.x;
     v[1] = q.y;
     v[2] = q.z;
   } else {
-    const uint32_t o8 = f.boff8 + i * 8u;
-    v[0] = ldo<double>(f.f[F_VX], o8);
-    v[1] = ldo<double>(f.f[F_VY], o8);
-    v[2] = ldo<double>(f.f[F_VZ], o8);
+    const Vel3d q = ldo<Vel3d>(f.f[F_VX], vel_off<P>(f, i));
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
   }
 }
 
 // byte offset of record i's id (from the id field's pointer)
 template <class P>
 __device__ __forceinline__ uint32_t id_off(const RecPtr& f, uint32_t i) {
-  if constexpr (std::is_same<P, P32>::value) return vel_off(f, i);
+  if constexpr (std::is_same<P, P32>::value) return vel_off<P>(f, i);
   else return f.boff4 + i * 4u;
 }
 
@@ -197,7 +198,7 @@ struct Part<P32> {
     const uint32_t o = f.boff4 + i * 4u;
     cell = ldo<int>(f.f[F32_CELL], o);
     off = ldo<float>(f.f[F32_OFF], o);
-    const uint4 v = ldo<uint4>(f.f[F_VX], vel_off(f, i));
+    const uint4 v = ldo<uint4>(f.f[F_VX], vel_off<P32>(f, i));
     vx = __uint_as_float(v.x);
     vy = __uint_as_float(v.y);
     vz = __uint_as_float(v.z);
@@ -211,11 +212,11 @@ struct Part<P64> {
   double x, vx, vy, vz;
   uint32_t id;
   __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
-    const uint32_t o8 = f.boff8 + i * 8u;
-    x = ldo<double>(f.f[F64_X], o8);
-    vx = ldo<double>(f.f[F_VX], o8);
-    vy = ldo<double>(f.f[F_VY], o8);
-    vz = ldo<double>(f.f[F_VZ], o8);
+    x = ldo<double>(f.f[F64_X], f.boff8 + i * 8u);
+    const Vel3d v = ldo<Vel3d>(f.f[F_VX], vel_off<P64>(f, i));
+    vx = v.x;
+    vy = v.y;
+    vz = v.z;
     id = ldo<uint32_t>(f.f[F_ID], f.boff4 + i * 4u);
   }
 };
@@ -234,15 +235,12 @@ __device__ __forceinline__ void store_record(const RecPtr& f, uint32_t i, int d,
   if constexpr (std::is_same<P, P32>::value) {
     sto<int>(f.f[F32_CELL], o4, d);
     sto<float>(f.f[F32_OFF], o4, pos);
-    sto<uint4>(f.f[F_VX], vel_off(f, i),
+    sto<uint4>(f.f[F_VX], vel_off<P32>(f, i),
                make_uint4(__float_as_uint(vx), __float_as_uint(vy), __float_as_uint(vz),
                           kWithId ? id : 0u));
   } else {
-    const uint32_t o8 = f.boff8 + i * 8u;
-    sto<double>(f.f[F64_X], o8, pos);
-    sto<double>(f.f[F_VX], o8, vx);
-    sto<double>(f.f[F_VY], o8, vy);
-    sto<double>(f.f[F_VZ], o8, vz);
+    sto<double>(f.f[F64_X], f.boff8 + i * 8u, pos);
+    sto<Vel3d>(f.f[F_VX], vel_off<P64>(f, i), Vel3d{vx, vy, vz});
     if constexpr (kWithId) sto<uint32_t>(f.f[F_ID], o4, id);
   }
 }
@@ -258,11 +256,10 @@ __device__ __forceinline__ void store_in_place(const RecPtr& f, uint32_t i, bool
   if constexpr (std::is_same<P, P32>::value) {
     sto<int>(f.f[F32_CELL], o4, alive ? d : -1);
     sto<float>(f.f[F32_OFF], o4, pos);
-    sto<float>(f.f[F_VX], vel_off(f, i), vx);
+    sto<float>(f.f[F_VX], vel_off<P32>(f, i), vx);
   } else {
-    const uint32_t o8 = f.boff8 + i * 8u;
-    sto<double>(f.f[F64_X], o8, alive ? pos : -1.0);
-    sto<double>(f.f[F_VX], o8, vx);
+    sto<double>(f.f[F64_X], f.boff8 + i * 8u, alive ? pos : -1.0);
+    sto<double>(f.f[F_VX], vel_off<P64>(f, i), vx);
   }
 }
 
@@ -420,7 +417,7 @@ struct PushIn<P32> {
     const uint32_t o = f.boff4 + i * 4u;
     cell = ldo<int>(f.f[F32_CELL], o);
     off = ldo<float>(f.f[F32_OFF], o);
-    vx = ldo<float>(f.f[F_VX], vel_off(f, i));
+    vx = ldo<float>(f.f[F_VX], vel_off<P32>(f, i));
   }
 };
 
@@ -428,9 +425,8 @@ template <>
 struct PushIn<P64> {
   double x, vx;
   __device__ __forceinline__ void load(const RecPtr& f, uint32_t i) {
-    const uint32_t o8 = f.boff8 + i * 8u;
-    x = ldo<double>(f.f[F64_X], o8);
-    vx = ldo<double>(f.f[F_VX], o8);
+    x = ldo<double>(f.f[F64_X], f.boff8 + i * 8u);
+    vx = ldo<double>(f.f[F_VX], vel_off<P64>(f, i));
   }
 };
 
@@ -2056,7 +2052,7 @@ __global__ __launch_bounds__(kWG) void k_emit(const SimDev* __restrict__ simp) {
   RecPtr out;
 #pragma unroll
   for (int k = 0; k < 6; ++k) out.f[k] = s.em_stage[k];
-  out.boff4 = out.boff8 = out.boff16 = 0u;
+  out.boff4 = out.boff8 = out.boffv = 0u;
   uint32_t n_wall[2] = {0u, 0u};
   for (int w = 0; w < kWaves; ++w) {
     const int unit = tt.y * kWaves + w;
@@ -2424,7 +2420,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(const SimDev* __restrict__ sim
       RecPtr src;
 #pragma unroll
       for (int k = 0; k < 6; ++k) src.f[k] = se.em_stage[k];
-      src.boff4 = src.boff8 = src.boff16 = 0u;
+      src.boff4 = src.boff8 = src.boffv = 0u;
       const RecPtr dst = rec_buf(&sim.sp[tt.x - 1], q);
       for (int w = 0; w < kWaves; ++w) {
         const int unit = u * kWaves + w;

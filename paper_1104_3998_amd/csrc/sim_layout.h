@@ -80,12 +80,14 @@ enum : int {
   DS_N = 8
 };
 
-// Per-particle record fields of the two layouts.  FP64: one array per field (x, vx, vy,
-// vz 8 bytes, id 4 bytes).  FP32: cell and offset in arrays of their own (4 bytes), and
-// vx, vy, vz, id together in one array of 16-byte records, so that the MCC pass writes a
-// collided particle's velocity with one store into one cache line; the field pointers
-// of vx, vy, vz and id then point 0, 4, 8 and 12 bytes into that array (element stride
-// 16 bytes).
+// Per-particle record fields of the two layouts.  The velocity is kept as one record per
+// particle, so that the MCC pass writes a collided particle's velocity with one store
+// into one cache line (two at most):
+// * FP32: cell and offset in arrays of their own (4 bytes each); vx, vy, vz, id together
+//   in an array of 16-byte records, the field pointers of vx, vy, vz and id pointing 0,
+//   4, 8 and 12 bytes into it (element stride 16 bytes);
+// * FP64: x and id in arrays of their own (8 and 4 bytes); vx, vy, vz in an array of
+//   24-byte records, their field pointers 0, 8 and 16 bytes into it (stride 24 bytes).
 enum : int { F32_CELL = 0, F32_OFF = 1, F_VX = 2, F_VY = 3, F_VZ = 4, F_ID = 5 };
 enum : int { F64_X = 0 };
 
@@ -103,7 +105,7 @@ struct SpeciesDev {
   // FP64: x, (unused), vx, vy, vz, id
   void GM* fld[2][6];
   uint32_t bstride4, bstride8;  // fld[1][f] - fld[0][f] in bytes for 4- and 8-byte fields
-  uint32_t bstride16;           // ... for the FP32 velocity records
+  uint32_t bstridev;            // ... for the velocity records (a multiple of the record size)
   // birth staging (electron species only): [0] secondary electrons, [1] new ions;
   // fields as in fld
   void GM* stage[2][6];
