@@ -551,8 +551,19 @@ def main():
         rb.update({"discharges": len(batch), "autotune": tune_rep})
         paths["batched"] = rb
         log("batched scan, discharges one at a time (every %dth)" % args.seq_every)
-        seq = sequential_sample(fs, torch, batch, tuning, args.path_steps, args.warmup,
-                                every=args.seq_every)
+        # alone, a discharge may prefer other tiles than the batch's tuned ones: the faster
+        # of the batch's geometry and the library's default is the baseline
+        seq_t = sequential_sample(fs, torch, batch, tuning, args.path_steps, args.warmup,
+                                  every=args.seq_every)
+        seq_t["geometry"] = "the batch's tuned geometry" if tuning else "library default"
+        seq = seq_t
+        if tuning:
+            seq_d = sequential_sample(fs, torch, batch, None, args.path_steps, args.warmup,
+                                      every=args.seq_every)
+            seq_d["geometry"] = "library default"
+            best, other = (seq_t, seq_d) if seq_t["value"] >= seq_d["value"] else (seq_d, seq_t)
+            seq = dict(best, other_geometry={"geometry": other["geometry"],
+                                             "value": other["value"]})
         seq["batched_over_sequential"] = rb["value"] / seq["value"]
         paths["batched"]["sequential"] = seq
     gate = None
