@@ -324,6 +324,9 @@ EDGE_STATES = {
     "single": dict(n=(1, 1)),
     # every electron a far mover (40-90 cells in one step against a 31-cell window)
     "all_far": dict(n=(4096, 4096), fast=(4096, 0)),
+    # every electron in one cell, all moving 60 cells one way or the other: two far groups
+    # of about 2048 into two cells (the ranking inside a cell's group is quadratic)
+    "pile_up": dict(n=(4096, 4096), cells=[10], fast=(4096, 0), fast_speed=(60.0, 60.0)),
 }
 
 
@@ -332,12 +335,14 @@ EDGE_STATES = {
 def test_edge_states_one_step(fspic, oracle_mod, case, precision):
     """One step from degenerate states against the oracle: the sort, deposit, MCC and
     solve on a single occupied cell, on empty cells and tiles, on one particle per
-    species, and with every electron beyond the sort window (far list sized for all)."""
+    species, with every electron beyond the sort window (far list sized for all), and
+    with every electron of one cell landing in one of two far cells."""
     e = EDGE_STATES[case]
     wl = workloads.periodic_c1()
     print("edge state", case, precision, flush=True)
     st = workloads.synthetic_state(wl["n_cells"], e["n"], precision, seed=41,
                                    vth=e.get("vth", (2.0, 0.02)), fast=e.get("fast", (0, 0)),
+                                   fast_speed=e.get("fast_speed", (40.0, 90.0)),
                                    cells=e.get("cells"))
     fp32 = precision == "fp32_offset"
     sim = fspic.Simulation(wl, precision, tuning={"far_capacity": 8192})
@@ -367,6 +372,7 @@ def test_edge_states_lagged_sort(fspic, oracle_mod, case, precision):
     print("edge state, lagged sort", case, precision, flush=True)
     st = workloads.synthetic_state(wl["n_cells"], e["n"], precision, seed=43,
                                    vth=e.get("vth", (2.0, 0.02)), fast=e.get("fast", (0, 0)),
+                                   fast_speed=e.get("fast_speed", (40.0, 90.0)),
                                    cells=e.get("cells"))
     fp32 = precision == "fp32_offset"
     sim = fspic.Simulation(wl, precision, tuning={"far_capacity": 8192})
