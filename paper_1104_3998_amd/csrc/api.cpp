@@ -953,7 +953,7 @@ static int fine_state_to_host(pic_sim* sim, const SpeciesDev& S, bool fp32, pic_
     if ((rc = fine_gather(sim, S, f[F32_CELL], st->cell[s], cnt))) return rc;
     if ((rc = fine_gather(sim, S, f[F32_OFF], st->off[s], cnt))) return rc;
     std::vector<VelRec> rec(static_cast<size_t>(n));
-    if ((rc = fine_gather(sim, S, f[F_VX], reinterpret_cast<VelRec*>(rec.data()), cnt))) return rc;
+    if ((rc = fine_gather(sim, S, f[F_VX], rec.data(), cnt))) return rc;
     for (size_t i = 0; i < rec.size(); ++i)
       split_vel(rec[i], i, st->vxf[s], st->vyf[s], st->vzf[s], st->id[s]);
     return PIC_OK;
